@@ -1,0 +1,129 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module only builds input data (grids, wavenumber fields, right-hand sides,
+random vectors).  It holds none of the solver's arithmetic, and it imports
+neither the HIP binding nor the CPU oracle, so both sides can be fed the same
+arrays.
+
+Workloads follow the paper's model problems (Section 2): the unit square with a
+constant wavenumber and a point source at the centre, with Dirichlet (MP-2a) or
+first-order Sommerfeld (MP-2b) boundaries.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+SEED = 230806152
+
+BC_DIRICHLET, BC_SOMMERFELD = 0, 1
+COARSE_GALERKIN, COARSE_REDGLK2 = 0, 1
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One problem instance: grid, wavenumber, boundary, source and method options."""
+    name: str
+    nx: int
+    ny: int
+    hx: float
+    hy: float
+    bc: int
+    kconst: float
+    source: str              # "point" or "gauss"
+    coarse_op: int
+    restart: int = 50
+    tol: float = 1e-6
+    coarse_restart: int = 30
+    coarse_tol: float = 1e-1
+    coarse_maxit: int = 300
+
+    @property
+    def npts(self) -> int:
+        return self.nx * self.ny
+
+    def rhs(self) -> np.ndarray:
+        ic, jc = (self.nx - 1) // 2, (self.ny - 1) // 2
+        if self.source == "point":
+            return point_source(self.nx, self.ny, self.hx, self.hy, ic, jc)
+        return gaussian_source(self.nx, self.ny, self.hx, self.hy, ic, jc, 2.0 * self.hx)
+
+
+def unit_square(n: int) -> tuple[int, int, float, float]:
+    """n x n vertex grid on [0,1]^2 including the boundary; h = 1/(n-1)."""
+    h = 1.0 / (n - 1)
+    return n, n, h, h
+
+
+def point_source(nx: int, ny: int, hx: float, hy: float, i: int, j: int) -> np.ndarray:
+    """Discrete unit point source: 1/(hx*hy) at node (i, j), so that the source
+    integrates to one over the cell (the delta of the model problems)."""
+    b = np.zeros((ny, nx), np.complex128)
+    b[j, i] = 1.0 / (hx * hy)
+    return b
+
+
+def gaussian_source(nx: int, ny: int, hx: float, hy: float, i: int, j: int,
+                    sigma: float) -> np.ndarray:
+    """Gaussian-smoothed point source of width sigma centred on node (i, j):
+    exp(-r^2 / 2 sigma^2) / (2 pi sigma^2) on nodes with r <= 8 sigma, zero
+    elsewhere, renormalised so that sum(b) * hx * hy = 1."""
+    b = np.zeros((ny, nx), np.complex128)
+    ri = int(math.ceil(8 * sigma / hx))
+    rj = int(math.ceil(8 * sigma / hy))
+    i0, i1 = max(0, i - ri), min(nx - 1, i + ri)
+    j0, j1 = max(0, j - rj), min(ny - 1, j + rj)
+    xs = (np.arange(i0, i1 + 1) - i) * hx
+    ys = (np.arange(j0, j1 + 1) - j) * hy
+    r2 = ys[:, None] ** 2 + xs[None, :] ** 2
+    g = np.exp(-r2 / (2 * sigma * sigma)) / (2 * math.pi * sigma * sigma)
+    g[r2 > (8 * sigma) ** 2] = 0.0
+    g /= g.sum() * hx * hy
+    b[j0:j1 + 1, i0:i1 + 1] = g
+    return b
+
+
+def random_complex(shape, seed: int = SEED) -> np.ndarray:
+    """Standard complex normal entries (real and imaginary parts N(0,1))."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def random_field(ny: int, nx: int, lo: float, hi: float, seed: int = SEED) -> np.ndarray:
+    """Smoothly varying positive field in [lo, hi] (a sum of a few seeded
+    Gaussian bumps on a linear trend), used as a variable wavenumber."""
+    rng = np.random.default_rng(seed)
+    y, x = np.meshgrid(np.linspace(0, 1, ny), np.linspace(0, 1, nx), indexing="ij")
+    f = 0.5 + 0.3 * (x - 0.5) + 0.2 * (y - 0.5)
+    for _ in range(3):
+        cx, cy = rng.uniform(0.2, 0.8, 2)
+        s = rng.uniform(0.08, 0.2)
+        f += rng.uniform(-0.3, 0.3) * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2 * s * s))
+    f = (f - f.min()) / (f.max() - f.min())
+    return lo + (hi - lo) * f
+
+
+# The two plain-method workloads.  The small one is the oracle-sized case
+# (MP-2a, Dirichlet, 129^2, k = 20, Galerkin coarse operator); the large one is
+# the throughput case (MP-2b-like, Sommerfeld, 4097^2, k = 800, re-discretised
+# higher-order coarse operator ReD-Glk2, Gaussian source of width 2h).
+def small_plain() -> Workload:
+    nx, ny, hx, hy = unit_square(129)
+    return Workload("mp2a_129_k20_galerkin", nx, ny, hx, hy, BC_DIRICHLET, 20.0, "point",
+                    COARSE_GALERKIN)
+
+
+def large_plain() -> Workload:
+    nx, ny, hx, hy = unit_square(4097)
+    return Workload("mp2b_4097_k800_redglk2", nx, ny, hx, hy, BC_SOMMERFELD, 800.0, "gauss",
+                    COARSE_REDGLK2)
+
+
+def scaled_plain(n: int, k: float, bc: int = BC_SOMMERFELD,
+                 coarse_op: int = COARSE_REDGLK2, source: str = "gauss") -> Workload:
+    """A plain-method workload on an n x n unit-square grid."""
+    nx, ny, hx, hy = unit_square(n)
+    return Workload(f"unit_{n}_k{k:g}_bc{bc}_c{coarse_op}", nx, ny, hx, hy, bc, k, source,
+                    coarse_op)
