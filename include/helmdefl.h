@@ -1,0 +1,191 @@
+/*
+ * helmdefl.h -- C-ABI of libhelmdefl.so, an MI355X (gfx950) solver for the 2D
+ * finite-difference Helmholtz problem with the matrix-free two-level deflation
+ * preconditioner of Chen, Dwarka & Vuik (arXiv 2308.06152).
+ *
+ * The problem (Section 2): -Lap u - k(x,y)^2 u = b on a rectangle, with
+ * homogeneous Dirichlet or first-order Sommerfeld (du/dn - i k u = 0)
+ * boundaries, discretised by the 5-point stencil on a vertex-centred grid
+ * (Section 2.1).  The preconditioner (Section 3) is A-DEF1 / APD:
+ *     P = M^{-1} (I - A Q) + Q,   Q = Z A_2h^{-1} Z^T,
+ * with M^{-1} one multigrid V-cycle for the complex shifted Laplacian
+ * M = -Lap - (beta_re + i beta_im) k^2 (damped Jacobi, full weighting, bilinear
+ * interpolation), Z the linear or higher-order (Bezier) deflation vectors, and
+ * A_2h the Galerkin (str-Glk) or re-discretised (ReD-Glk2) coarse operator,
+ * inverted by CSLP-preconditioned GMRES (Section 5.2).
+ *
+ * Conventions shared by every entry point
+ *  - Vectors are complex128, real/imaginary interleaved (the memory layout of
+ *    torch.complex128 / std::complex<double>), stored [ny][nx] with x fastest;
+ *    node (i,j) is at (i*hx, j*hy), boundary nodes included.  With nrhs > 1 the
+ *    right-hand sides are nrhs contiguous [ny][nx] blocks.
+ *  - Every vector argument is a DEVICE pointer on the current HIP device, owned
+ *    by the caller, at least 16-byte aligned.  Inputs and outputs must not
+ *    overlap.  The library keeps no pointer after a call returns.
+ *  - Homogeneous Dirichlet boundary nodes are not unknowns: every operator
+ *    writes 0 there and ignores the values it is given there.
+ *  - Calls are asynchronous on the handle's stream, except helm_solve and
+ *    helm_coarse_solve, which synchronise that stream (they read Krylov scalars
+ *    back to the host every iteration) and fill their info before returning.
+ *  - Return value: HELM_OK (0) or a negative helm_status.  No C++ exception
+ *    crosses the ABI.  On an error the output buffers are unspecified, except
+ *    for HELM_ENOCONV (see helm_solve).
+ */
+#ifndef HELMDEFL_H
+#define HELMDEFL_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HELM_OK = 0,
+    HELM_EINVAL = -1,     /* null pointer, bad size or option                    */
+    HELM_EGRID = -2,      /* grid cannot be coarsened as deflation/multigrid need */
+    HELM_ENONFINITE = -3, /* NaN or Inf in k or in a right-hand side              */
+    HELM_ENOMEM = -4,     /* device or host allocation failed                    */
+    HELM_EHIP = -5,       /* a HIP runtime call or kernel launch failed          */
+    HELM_ENOCONV = -6     /* solver stopped at maxit above the tolerance         */
+} helm_status;
+
+enum { HELM_BC_DIRICHLET = 0, HELM_BC_SOMMERFELD = 1 };
+enum { HELM_DEFL_Q = 0, HELM_DEFL_P = 1, HELM_DEFL_ADEF1 = 2 };
+enum { HELM_Z_LINEAR = 0, HELM_Z_HIGH = 1 };
+enum { HELM_COARSE_GALERKIN = 0, HELM_COARSE_REDGLK2 = 1 };
+enum { HELM_CMODE_FIXED = 1, HELM_CMODE_TOL = 2 };
+
+/* The grid: nx x ny vertex nodes including the boundary, spacings hx, hy
+ * (Section 2.1 takes hx = hy = h; ReD-Glk2 requires hx == hy). */
+typedef struct {
+    int nx, ny;
+    double hx, hy;
+    int bc; /* HELM_BC_* on all four sides */
+} helm_grid;
+
+/* Method options; helm_opts_default() fills the paper's values. */
+typedef struct {
+    double beta_re, beta_im; /* CSLP shift, default (1, 0.5) (Section 3.1)      */
+    double omega;            /* damped-Jacobi relaxation, default 0.8           */
+    int nu_pre, nu_post;     /* smoothing sweeps; only 1/1 is supported         */
+    int defl_vectors;        /* HELM_Z_*, default HELM_Z_HIGH (APD)             */
+    int coarse_op;           /* HELM_COARSE_*, default HELM_COARSE_GALERKIN     */
+    int coarse_mode;         /* HELM_CMODE_*, default HELM_CMODE_TOL            */
+    int coarse_iters;        /* FIXED: iteration count; TOL: cap (default 300)  */
+    int coarse_restart;      /* inner GMRES restart length (default 30)         */
+    double coarse_tol;       /* TOL: relative residual target (default 1e-1)    */
+    int restart;             /* outer FGMRES restart length (default 50)        */
+    int maxit;               /* outer iteration cap (default 1000)              */
+    double tol;              /* outer relative residual target (default 1e-6)   */
+    int x0_given;            /* helm_solve: 1 = x holds the initial guess       */
+    int force_iters;         /* >0: run exactly this many outer iterations      */
+} helm_opts;
+
+/* Per right-hand side result of helm_solve. */
+typedef struct {
+    int outer_iters;       /* preconditioner applications, over all restarts     */
+    int inner_iters_total; /* coarse-grid GMRES iterations, summed               */
+    int inner_iters_max;   /* largest single coarse solve                        */
+    int converged;         /* relres <= tol                                      */
+    double relres;         /* ||b - A x|| / ||b|| recomputed in FP64 at exit     */
+    double t_solve_ms;     /* wall time of this right-hand side                  */
+} helm_solve_info;
+
+typedef struct helm_ctx helm_ctx;
+
+/* Fill *o with the defaults listed above.  HELM_EINVAL if o is NULL. */
+int helm_opts_default(helm_opts *o);
+
+/* Create a solver handle.
+ *  g        grid; nx, ny >= 5 and odd (the deflation coarse grid is
+ *           ((nx+1)/2) x ((ny+1)/2), Section 4), else HELM_EGRID.  Multigrid
+ *           levels coarsen while both counts are odd and >= 5; the coarsest
+ *           level (at most 2048 nodes) is solved exactly.
+ *  k_dev    device pointer to the real FP64 wavenumber field [ny][nx]
+ *           (k = 2 pi f / c, Section 2), or NULL to use k_const everywhere.
+ *           Copied at create; not retained.
+ *  opts     options, or NULL for the defaults.
+ *  stream   hipStream_t for every call on this handle (NULL = null stream).
+ * Allocates the level hierarchy and the coarse-solve workspace on the device.
+ * HELM_ENONFINITE if k has a non-finite or negative value. */
+int helm_create(const helm_grid *g, const double *k_dev, double k_const, const helm_opts *opts,
+                void *stream, helm_ctx **out);
+
+/* y = A_h x: the 5-point Helmholtz operator with the boundary closure of
+ * Section 2.1 (Sommerfeld ghost nodes eliminated: -2ik/h on the diagonal per
+ * boundary direction, inward neighbour -2/h^2), the matrix-free matvec of
+ * Section 5.1. */
+int helm_apply(helm_ctx *h, const void *x, void *y, int nrhs);
+
+/* z = V(r): one CSLP multigrid V-cycle (Sections 3.1 and 5.1) for
+ * M = -Lap - (beta_re + i beta_im) k^2, re-discretised on every level with the
+ * injected wavenumber; 1 damped-Jacobi pre- and post-sweep from x = 0, full
+ * weighting, bilinear interpolation, exact solve on the coarsest level. */
+int cslp_vcycle(helm_ctx *h, const void *r, void *z, int nrhs);
+
+/* Deflation applied to v (Sections 3.2.2 and 5.2): with v1 = Z^T v,
+ * v2 ~= A_2h^{-1} v1 (per coarse_mode), v' = Z v2:
+ *   HELM_DEFL_Q:     w = v'
+ *   HELM_DEFL_P:     w = v - A_h v'
+ *   HELM_DEFL_ADEF1: w = V(v - A_h v') + v'   (the preconditioner P_A-DEF1) */
+int deflate_apply(helm_ctx *h, int mode, const void *v, void *w, int nrhs);
+
+/* Solve A_h x = b by flexible GMRES(restart), right-preconditioned with
+ * P_A-DEF1, to ||b - A x|| / ||b|| <= tol (true residual, checked at every
+ * restart).  x: output, and input when opts.x0_given.  info: array of nrhs
+ * entries, may be NULL.  HELM_ENOCONV when maxit was reached above tol; x then
+ * holds the last iterate and info is filled.  HELM_ENONFINITE if b is not
+ * finite. */
+int helm_solve(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *info);
+
+/* Free the handle and its device memory (after synchronising its stream). */
+int helm_destroy(helm_ctx *h);
+
+/* Static text for a helm_status code. */
+const char *helm_strerror(int code);
+
+/* ---- Steps of the path, exported for step-by-step parity checks ---------- */
+
+/* Dimensions of the deflation coarse grid (= multigrid level 1). */
+int helm_coarse_dims(helm_ctx *h, int *nxc, int *nyc);
+/* Number of multigrid levels (level 0 is the fine grid). */
+int helm_num_levels(helm_ctx *h, int *nlev);
+/* Dimensions of multigrid level l, 0 <= l < nlev. */
+int helm_level_dims(helm_ctx *h, int l, int *nx, int *ny);
+/* vc = Z^T vf (fine -> coarse): [1 4 6 4 1]/8 (higher order) or 1/2 [1 2 1]
+ * (linear) per axis, truncated at the boundary (Sections 3.2, 3.2.1). */
+int helm_z_restrict(helm_ctx *h, const void *vf, void *vc);
+/* vf = Z vc (coarse -> fine), the transpose of helm_z_restrict. */
+int helm_z_prolong(helm_ctx *h, const void *vc, void *vf);
+/* y = A_2h x on the coarse grid: Z^T A_h Z (str-Glk, Section 5.2.1) or the
+ * ReD-Glk2 re-discretisation (Section 5.2.4). */
+int helm_coarse_apply(helm_ctx *h, const void *x, void *y);
+/* v2 ~= A_2h^{-1} v1 by right-preconditioned GMRES(coarse_restart) with a
+ * V-cycle starting on the coarse grid, x0 = 0 (FIXED or TOL mode).
+ * *iters receives the iteration count (may be NULL).  Synchronises. */
+int helm_coarse_solve(helm_ctx *h, const void *v1, void *v2, int *iters);
+
+/* ---- Kernel timing (HIP events on the handle's stream) ------------------- */
+
+/* Kernel classes that can be timed. */
+enum {
+    HELM_K_APPLY = 0,     /* 5-point operator                      */
+    HELM_K_VC_DOWN = 1,   /* fused pre-smooth/residual/restriction */
+    HELM_K_VC_UP = 2,     /* fused interpolation/post-smooth       */
+    HELM_K_ZT = 3,        /* Z^T restriction                       */
+    HELM_K_DRESID = 4,    /* t = v - A_h Z v2                      */
+    HELM_K_COARSE = 5,    /* coarse operator A_2h                  */
+    HELM_K_DOT = 6,       /* block dot products V^H w              */
+    HELM_K_UPDATE = 7,    /* w -= V c                              */
+    HELM_K_NCLASSES = 8
+};
+/* Start timing launches of kernel class `kclass` on multigrid level `level`
+ * (-1 = any level).  Resets the accumulators.  kclass < 0 disables timing. */
+int helm_timing_enable(helm_ctx *h, int kclass, int level);
+/* Read the accumulated launch count, summed event time (ms) and the summed
+ * algorithmic HBM bytes of the timed launches (synchronises the stream). */
+int helm_timing_read(helm_ctx *h, long long *launches, double *total_ms, double *alg_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,147 @@
+// hd_common.h -- types and launch wrappers shared by the HIP kernels and the
+// host driver of libhelmdefl.so (gfx950).  Complex128 values are double2
+// (x = real, y = imaginary), 16-byte aligned, interleaved as in the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace hd {
+
+typedef double2 cd;
+
+enum { BC_DIR = 0, BC_SOM = 1 };
+
+// Partial-sum stride of the block reductions: at most 63 dot products plus one
+// norm slot per block.
+constexpr int PSTRIDE = 64;
+constexpr int MAX_RESTART = 60;
+
+// One grid level as the kernels see it (passed by value).
+struct Lev {
+    int nx, ny;
+    double hx, hy;
+    double ihx2, ihy2;  // 1/hx^2, 1/hy^2
+    int bc;
+    const double *k;    // wavenumber [ny][nx] on this level, or nullptr
+    double kc;          // constant wavenumber when k == nullptr
+};
+
+inline Lev make_lev(int nx, int ny, double hx, double hy, int bc, const double *k, double kc)
+{
+    Lev L;
+    L.nx = nx;
+    L.ny = ny;
+    L.hx = hx;
+    L.hy = hy;
+    L.ihx2 = 1.0 / (hx * hx);
+    L.ihy2 = 1.0 / (hy * hy);
+    L.bc = bc;
+    L.k = k;
+    L.kc = kc;
+    return L;
+}
+
+__host__ __device__ inline double kat(const Lev &L, int i, int j)
+{
+    return L.k ? L.k[(size_t)j * L.nx + i] : L.kc;
+}
+
+__host__ __device__ inline bool unknown(const Lev &L, int i, int j)
+{
+    return L.bc == BC_SOM || (i > 0 && j > 0 && i < L.nx - 1 && j < L.ny - 1);
+}
+
+// Multipliers of the 5-point operator -Lap - s k^2 at node (i,j) (Section 2.1
+// stencil; Section 5.1 names them ap, aw, ae, as, an).  Sommerfeld: the ghost
+// node beyond a boundary node is eliminated (u_ghost = u_inward + 2ikh u_bnd),
+// adding -2ik/h to ap and doubling the inward coupling, per direction.
+// Dirichlet: boundary nodes are not unknowns (returns false); couplings to
+// them are dropped.  (i,j) must lie inside the grid.
+__host__ __device__ inline bool coef5(const Lev &L, cd s, int i, int j, cd &ap, double &aw,
+                                      double &ae, double &as, double &an)
+{
+    const double k = kat(L, i, j);
+    const double k2 = k * k;
+    ap = make_double2(2.0 * L.ihx2 + 2.0 * L.ihy2 - s.x * k2, -s.y * k2);
+    aw = -L.ihx2;
+    ae = -L.ihx2;
+    as = -L.ihy2;
+    an = -L.ihy2;
+    if (L.bc == BC_SOM) {
+        if (i == 0) {
+            ap.y -= 2.0 * k / L.hx;
+            ae += aw;
+            aw = 0.0;
+        }
+        if (i == L.nx - 1) {
+            ap.y -= 2.0 * k / L.hx;
+            aw += ae;
+            ae = 0.0;
+        }
+        if (j == 0) {
+            ap.y -= 2.0 * k / L.hy;
+            an += as;
+            as = 0.0;
+        }
+        if (j == L.ny - 1) {
+            ap.y -= 2.0 * k / L.hy;
+            as += an;
+            an = 0.0;
+        }
+        return true;
+    }
+    if (i == 0 || j == 0 || i == L.nx - 1 || j == L.ny - 1) return false;
+    if (i == 1) aw = 0.0;
+    if (i == L.nx - 2) ae = 0.0;
+    if (j == 1) as = 0.0;
+    if (j == L.ny - 2) an = 0.0;
+    return true;
+}
+
+// ---- launch wrappers (kernels.hip); all return the launch's hipError_t ----
+
+// y = (-Lap - s k^2) x, or y = b - (-Lap - s k^2) x when b != nullptr.
+hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hipStream_t st);
+// rc = FW( r - M (omega D^-1 r) ): pre-smooth from zero, residual, restriction.
+hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r, cd *rc,
+                          hipStream_t st);
+// out (+)= x2 + omega D^-1 (r - M x2), x2 = omega D^-1 r + P ec  [+ Z v2].
+hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
+                        const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
+                        hipStream_t st);
+// x = Minv r on the coarsest level (dense inverse, n x n, row major).
+hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st);
+// vc = Z^T vf, or vc = b - Z^T vf when b != nullptr.
+hipError_t launch_zt(const Lev &Lf, const Lev &Lc, int zho, const cd *vf, const cd *b, cd *vc,
+                     hipStream_t st);
+// vf = Z vc.
+hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf, hipStream_t st);
+// t = v - A_h (Z v2).
+hipError_t launch_dresid(const Lev &Lf, const Lev &Lc, int zho, const cd *v, const cd *v2,
+                         cd *t, hipStream_t st);
+// y = A_2h x (ReD-Glk2) or y = b - A_2h x; interior and boundary band.
+hipError_t launch_redglk2(const Lev &Lc, const cd *x, const cd *b, cd *y, hipStream_t st);
+
+// ---- Krylov kernels ----
+// Number of partial-sum blocks used for vectors of length n.
+int krylov_blocks(size_t n);
+// part[blk][i] = sum conj(V_i) w over the block, i < m; slot m = |w|^2 if with_norm.
+hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd *part,
+                       int with_norm, hipStream_t st);
+// w -= sum_i c_i V_i; part[blk][0] = |w_new|^2 partial if part != nullptr.
+hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *part,
+                          hipStream_t st);
+// out[i] (=|+=) sum_blk part[blk][i], i < m; mode 2: out[0] = (sqrt(sum re), 0).
+hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, hipStream_t st);
+// v = w / nrm[0].x (v = 0 if the norm is 0).
+hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t st);
+// out (+)= sum_i y_i V_i.
+hipError_t launch_lincomb(const cd *V, size_t ld, int m, const cd *y, cd *out, size_t n,
+                          int accumulate, hipStream_t st);
+// p[0..n) = 0.
+hipError_t launch_zero(cd *p, size_t n, hipStream_t st);
+// out = in with the non-unknown (Dirichlet boundary) entries set to zero.
+hipError_t launch_mask_copy(const Lev &L, const cd *in, cd *out, hipStream_t st);
+
+}  // namespace hd

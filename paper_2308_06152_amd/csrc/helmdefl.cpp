@@ -1,0 +1,946 @@
+// helmdefl.cpp -- host side of libhelmdefl.so: the solver handle, the level
+// hierarchy, the V-cycle / deflation / Krylov drivers that sequence the HIP
+// kernels, and the C-ABI of include/helmdefl.h.
+//
+// Every arithmetic step of the solve runs in the kernels of kernels.hip; the
+// host only launches them, reads the Krylov scalars back (one small copy per
+// Arnoldi step) and does the O(m^2) Givens / least-squares work of GMRES.
+#include "helmdefl.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hd_common.h"
+
+using namespace hd;
+typedef std::complex<double> zc;
+
+namespace {
+
+constexpr int MAXLEV = 40;
+constexpr int MAX_COARSEST = 2048;  // nodes of the coarsest multigrid level
+constexpr int HBUF = 2 * PSTRIDE + 2;  // h1[64], h2[64], norm, spare
+
+#define HCHK(call)                                   \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return HELM_EHIP;      \
+    } while (0)
+#define RCHK(call)                    \
+    do {                              \
+        int r_ = (call);              \
+        if (r_ != HELM_OK) return r_; \
+    } while (0)
+
+struct LevelH {
+    int nx = 0, ny = 0;
+    double hx = 0, hy = 0;
+    double *kdev = nullptr;  // per-level wavenumber (nullptr: constant)
+    cd *r = nullptr;         // V-cycle right-hand side on this level (l >= 1)
+    cd *x = nullptr;         // V-cycle correction on this level (l >= 1)
+    size_t n() const { return (size_t)nx * (size_t)ny; }
+};
+
+// Host-side GMRES least-squares state: Hessenberg columns reduced by complex
+// Givens rotations.
+struct Givens {
+    int m;
+    std::vector<zc> H, g, sn;
+    std::vector<double> cs;
+    explicit Givens(int m_) : m(m_), H((size_t)(m_ + 1) * m_), g(m_ + 1), sn(m_), cs(m_) {}
+    void start(double beta)
+    {
+        std::fill(g.begin(), g.end(), zc(0));
+        g[0] = beta;
+    }
+    zc &h(int i, int j) { return H[(size_t)i * m + j]; }
+    // column j holds h(0..j, j); hn = h(j+1, j) >= 0.  Returns |g_{j+1}|.
+    double add_column(int j, const zc *col, double hn)
+    {
+        for (int i = 0; i <= j; i++) h(i, j) = col[i];
+        for (int i = 0; i < j; i++) {
+            const zc a = h(i, j), b = h(i + 1, j);
+            h(i, j) = cs[i] * a + sn[i] * b;
+            h(i + 1, j) = -std::conj(sn[i]) * a + cs[i] * b;
+        }
+        const zc a = h(j, j);
+        const double aa = std::abs(a);
+        if (hn == 0.0) {
+            cs[j] = 1.0;
+            sn[j] = 0.0;
+        } else if (aa == 0.0) {
+            cs[j] = 0.0;
+            sn[j] = 1.0;
+        } else {
+            const double rho = std::sqrt(aa * aa + hn * hn);
+            cs[j] = aa / rho;
+            sn[j] = (a / aa) * hn / rho;
+        }
+        h(j, j) = cs[j] * a + sn[j] * hn;
+        g[j + 1] = -std::conj(sn[j]) * g[j];
+        g[j] = cs[j] * g[j];
+        return std::abs(g[j + 1]);
+    }
+    void solve(int jend, std::vector<zc> &y)
+    {
+        y.assign(jend, zc(0));
+        for (int i = jend - 1; i >= 0; i--) {
+            zc s = g[i];
+            for (int q = i + 1; q < jend; q++) s -= h(i, q) * y[q];
+            y[i] = s / h(i, i);
+        }
+    }
+};
+
+}  // namespace
+
+struct helm_ctx {
+    helm_grid g{};
+    helm_opts o{};
+    hipStream_t st = nullptr;
+    double kconst = 0;
+    int nlev = 0;
+    LevelH L[MAXLEV];
+    cd shift = make_double2(1.0, 0.5);
+    int zho = 1;
+
+    // coarsest level dense inverse
+    cd *cinv = nullptr;
+    int ncoarsest = 0;
+
+    // deflation workspace (coarse grid = level 1)
+    cd *v1 = nullptr, *v2 = nullptr, *tf = nullptr, *f1 = nullptr, *f2 = nullptr;
+    // inner GMRES
+    int mc = 0;
+    cd *Vc = nullptr, *wc = nullptr, *zc_ = nullptr, *xin = nullptr;
+    // reductions
+    cd *part = nullptr;
+    int part_blocks = 0;
+    cd *hbuf = nullptr, *ydev = nullptr;
+    cd *hpin = nullptr;
+    // outer FGMRES (allocated on first solve)
+    int m = 0;
+    cd *V = nullptr, *Z = nullptr, *w = nullptr, *bm = nullptr;
+
+    // kernel timing
+    int t_cls = -1, t_lev = -1;
+    std::vector<hipEvent_t> ev_free;
+    struct Pend {
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Pend> pend;
+    long long t_count = 0;
+    double t_ms = 0, t_bytes = 0;
+
+    Lev lev(int l) const
+    {
+        const LevelH &q = L[l];
+        return make_lev(q.nx, q.ny, q.hx, q.hy, g.bc, q.kdev, kconst);
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// kernel timing: events around launches of one kernel class / level
+// ---------------------------------------------------------------------------
+int timing_flush(helm_ctx *h)
+{
+    if (h->pend.empty()) return HELM_OK;
+    HCHK(hipStreamSynchronize(h->st));
+    for (auto &p : h->pend) {
+        float ms = 0;
+        HCHK(hipEventElapsedTime(&ms, p.a, p.b));
+        h->t_ms += ms;
+        h->t_bytes += p.bytes;
+        h->t_count++;
+        h->ev_free.push_back(p.a);
+        h->ev_free.push_back(p.b);
+    }
+    h->pend.clear();
+    return HELM_OK;
+}
+
+struct Timed {
+    helm_ctx *h;
+    bool on;
+    hipEvent_t a{}, b{};
+    double bytes;
+    Timed(helm_ctx *h_, int cls, int level, double bytes_) : h(h_), on(false), bytes(bytes_)
+    {
+        if (h->t_cls != cls || (h->t_lev >= 0 && h->t_lev != level)) return;
+        if (h->pend.size() >= 4096 && timing_flush(h) != HELM_OK) return;
+        for (int q = 0; q < 2; q++) {
+            hipEvent_t e;
+            if (!h->ev_free.empty()) {
+                e = h->ev_free.back();
+                h->ev_free.pop_back();
+            } else if (hipEventCreate(&e) != hipSuccess) {
+                return;
+            }
+            (q == 0 ? a : b) = e;
+        }
+        on = hipEventRecord(a, h->st) == hipSuccess;
+    }
+    ~Timed()
+    {
+        if (!on) return;
+        (void)hipEventRecord(b, h->st);
+        h->pend.push_back({a, b, bytes});
+    }
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+template <class T>
+int dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) return HELM_OK;
+    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return HELM_ENOMEM;
+    }
+    return HELM_OK;
+}
+
+void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+bool coarsenable(int nx, int ny) { return nx >= 5 && ny >= 5 && (nx & 1) && (ny & 1); }
+
+// ||v|| of a device vector (synchronises).
+int vnorm(helm_ctx *h, const cd *v, size_t n, double *out)
+{
+    const int nb = krylov_blocks(n);
+    HCHK(launch_mdot(nullptr, 0, 0, v, n, h->part, 1, h->st));
+    HCHK(launch_reduce(h->part, nb, 1, h->hbuf + 2 * PSTRIDE, 2, h->st));
+    HCHK(hipMemcpyAsync(h->hpin + 2 * PSTRIDE, h->hbuf + 2 * PSTRIDE, sizeof(cd),
+                        hipMemcpyDeviceToHost, h->st));
+    HCHK(hipStreamSynchronize(h->st));
+    *out = h->hpin[2 * PSTRIDE].x;
+    return HELM_OK;
+}
+
+// Arnoldi step by classical Gram-Schmidt with one reorthogonalisation (CGS2):
+// w is orthogonalised against V[0..j1-1], V[j1] = w / ||w||; col[0..j1-1]
+// receives the projections, *hn the norm.  One device->host copy, then sync.
+int arnoldi_cgs2(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col, double *hn,
+                 int lev)
+{
+    const int nb = krylov_blocks(n);
+    cd *h1 = h->hbuf, *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
+    for (int pass = 0; pass < 2; pass++) {
+        cd *hc = pass == 0 ? h1 : h2;
+        {
+            Timed tm(h, HELM_K_DOT, lev, 16.0 * (j1 + 1) * n);
+            HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h->st));
+        }
+        HCHK(launch_reduce(h->part, nb, j1, hc, 0, h->st));
+        {
+            Timed tm(h, HELM_K_UPDATE, lev, 16.0 * (j1 + 2) * n);
+            HCHK(launch_mupdate(w, V, ld, j1, hc, n, pass == 1 ? h->part : nullptr, h->st));
+        }
+    }
+    HCHK(launch_reduce(h->part, nb, 1, nr, 2, h->st));
+    HCHK(launch_scale(w, nr, V + (size_t)j1 * ld, n, h->st));
+    HCHK(hipMemcpyAsync(h->hpin, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd), hipMemcpyDeviceToHost,
+                        h->st));
+    HCHK(hipStreamSynchronize(h->st));
+    for (int i = 0; i < j1; i++)
+        col[i] = zc(h->hpin[i].x + h->hpin[PSTRIDE + i].x, h->hpin[i].y + h->hpin[PSTRIDE + i].y);
+    *hn = h->hpin[2 * PSTRIDE].x;
+    return HELM_OK;
+}
+
+int upload_y(helm_ctx *h, const std::vector<zc> &y)
+{
+    for (size_t i = 0; i < y.size(); i++) h->hpin[i] = make_double2(y[i].real(), y[i].imag());
+    HCHK(hipMemcpyAsync(h->ydev, h->hpin, y.size() * sizeof(cd), hipMemcpyHostToDevice, h->st));
+    // the pinned staging buffer is reused by the next readback: wait for the copy
+    HCHK(hipStreamSynchronize(h->st));
+    return HELM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operators
+// ---------------------------------------------------------------------------
+int apply_A(helm_ctx *h, int l, const cd *x, const cd *b, cd *y)
+{
+    const Lev Lv = h->lev(l);
+    Timed tm(h, HELM_K_APPLY, l, (b ? 48.0 : 32.0) * h->L[l].n());
+    HCHK(launch_apply5(Lv, make_double2(1.0, 0.0), x, b, y, h->st));
+    return HELM_OK;
+}
+
+// z (+)= V-cycle(r) starting on level l0; on level 0 the last pass may add
+// Z v2 (v2 on level 1).
+int vcycle(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2)
+{
+    const int Lc = h->nlev - 1;
+    if (l0 == Lc) {
+        HCHK(launch_coarsest(h->ncoarsest, h->cinv, r, accumulate ? h->L[Lc].x : z, h->st));
+        if (accumulate) HCHK(launch_lincomb(h->L[Lc].x, 0, 1, h->hbuf + 2 * PSTRIDE + 1, z,
+                                            h->L[Lc].n(), 1, h->st));
+        return HELM_OK;
+    }
+    const cd *rin = r;
+    for (int l = l0; l < Lc; l++) {
+        Timed tm(h, HELM_K_VC_DOWN, l, 16.0 * h->L[l].n() + 16.0 * h->L[l + 1].n());
+        HCHK(launch_vc_down(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, rin, h->L[l + 1].r,
+                            h->st));
+        rin = h->L[l + 1].r;
+    }
+    HCHK(launch_coarsest(h->ncoarsest, h->cinv, h->L[Lc].r, h->L[Lc].x, h->st));
+    for (int l = Lc - 1; l >= l0; l--) {
+        const bool top = l == l0;
+        const cd *rl = top ? r : h->L[l].r;
+        cd *out = top ? z : h->L[l].x;
+        const int acc = top ? accumulate : 0;
+        const cd *vv = top ? v2 : nullptr;
+        const double by = (32.0 + 16.0 * acc) * h->L[l].n() + 16.0 * h->L[l + 1].n() * (vv ? 2 : 1);
+        Timed tm(h, HELM_K_VC_UP, l, by);
+        HCHK(launch_vc_up(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, rl, h->L[l + 1].x, out,
+                          acc, vv, h->zho, h->st));
+    }
+    return HELM_OK;
+}
+
+// y = A_2h x  or  y = b - A_2h x
+int coarse_apply(helm_ctx *h, const cd *x, const cd *b, cd *y)
+{
+    const Lev Lf = h->lev(0), Lc = h->lev(1);
+    const size_t nc = h->L[1].n(), nf = h->L[0].n();
+    if (h->o.coarse_op == HELM_COARSE_REDGLK2) {
+        Timed tm(h, HELM_K_COARSE, 1, (b ? 48.0 : 32.0) * nc);
+        HCHK(launch_redglk2(Lc, x, b, y, h->st));
+        return HELM_OK;
+    }
+    Timed tm(h, HELM_K_COARSE, 1, (b ? 48.0 : 32.0) * nc + 64.0 * nf);
+    HCHK(launch_z(Lf, Lc, h->zho, x, h->f1, h->st));
+    HCHK(launch_apply5(Lf, make_double2(1.0, 0.0), h->f1, nullptr, h->f2, h->st));
+    HCHK(launch_zt(Lf, Lc, h->zho, h->f2, b, y, h->st));
+    return HELM_OK;
+}
+
+// x ~= A_2h^{-1} b: right-preconditioned restarted GMRES, preconditioner = a
+// V-cycle starting on level 1, x0 = 0.  FIXED mode runs exactly coarse_iters
+// iterations; TOL mode stops at |g_{j+1}| <= coarse_tol ||b|| (checked on the
+// true residual at every restart) or at coarse_iters.
+int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
+{
+    const size_t nc = h->L[1].n();
+    const int m = h->mc;
+    const bool fixed = h->o.coarse_mode == HELM_CMODE_FIXED;
+    const int cap = h->o.coarse_iters;
+    const double tol = h->o.coarse_tol;
+    int it = 0;
+    if (iters) *iters = 0;
+    double bnorm;
+    RCHK(vnorm(h, b, nc, &bnorm));
+    HCHK(launch_zero(x, nc, h->st));
+    if (!std::isfinite(bnorm)) return HELM_ENONFINITE;
+    if (bnorm == 0.0) return HELM_OK;
+    Givens gv(m);
+    std::vector<zc> col(m + 1), y;
+    bool first = true;
+    for (;;) {
+        double beta;
+        const cd *r;
+        if (first) {
+            r = b;
+            beta = bnorm;
+        } else {
+            RCHK(coarse_apply(h, x, b, h->wc));
+            RCHK(vnorm(h, h->wc, nc, &beta));
+            r = h->wc;
+        }
+        if (!fixed && beta <= tol * bnorm) break;
+        if (it >= cap || beta == 0.0) break;
+        // V_0 = r / beta (the norm is in the device slot written by vnorm)
+        HCHK(launch_scale(r, h->hbuf + 2 * PSTRIDE, h->Vc, nc, h->st));
+        gv.start(beta);
+        int jend = 0;
+        bool stop = false;
+        for (int j = 0; j < m && it < cap; j++) {
+            cd *vj = h->Vc + (size_t)j * nc;
+            RCHK(vcycle(h, 1, vj, h->zc_, 0, nullptr));
+            RCHK(coarse_apply(h, h->zc_, nullptr, h->wc));
+            double hn;
+            RCHK(arnoldi_cgs2(h, h->Vc, nc, j + 1, h->wc, nc, col.data(), &hn, 1));
+            const double res = gv.add_column(j, col.data(), hn);
+            it++;
+            jend = j + 1;
+            if (!fixed && res <= tol * bnorm) {
+                stop = true;
+                break;
+            }
+            if (hn == 0.0) {
+                stop = true;
+                break;
+            }
+        }
+        gv.solve(jend, y);
+        RCHK(upload_y(h, y));
+        HCHK(launch_lincomb(h->Vc, nc, jend, h->ydev, h->wc, nc, 0, h->st));
+        RCHK(vcycle(h, 1, h->wc, x, 1, nullptr));
+        if (it >= cap) break;
+        if (stop && fixed) break;
+        first = false;
+    }
+    if (iters) *iters = it;
+    return HELM_OK;
+}
+
+// w = Q v, (I - A Q) v or P_A-DEF1 v for one vector on level 0.
+int deflate_one(helm_ctx *h, int mode, const cd *v, cd *w, int *inner)
+{
+    const Lev Lf = h->lev(0), Lc = h->lev(1);
+    const size_t nf = h->L[0].n(), nc = h->L[1].n();
+    {
+        Timed tm(h, HELM_K_ZT, 0, 16.0 * nf + 16.0 * nc);
+        HCHK(launch_zt(Lf, Lc, h->zho, v, nullptr, h->v1, h->st));
+    }
+    RCHK(coarse_solve(h, h->v1, h->v2, inner));
+    if (mode == HELM_DEFL_Q) {
+        HCHK(launch_z(Lf, Lc, h->zho, h->v2, w, h->st));
+        return HELM_OK;
+    }
+    cd *t = mode == HELM_DEFL_P ? w : h->tf;
+    {
+        Timed tm(h, HELM_K_DRESID, 0, 32.0 * nf + 16.0 * nc);
+        HCHK(launch_dresid(Lf, Lc, h->zho, v, h->v2, t, h->st));
+    }
+    if (mode == HELM_DEFL_P) return HELM_OK;
+    return vcycle(h, 0, t, w, 0, h->v2);
+}
+
+int ensure_outer(helm_ctx *h)
+{
+    if (h->V) return HELM_OK;
+    const size_t n = h->L[0].n();
+    const int m = h->o.restart;
+    int rc;
+    if ((rc = dalloc(&h->V, (size_t)(m + 1) * n)) || (rc = dalloc(&h->Z, (size_t)m * n)) ||
+        (rc = dalloc(&h->w, n)) || (rc = dalloc(&h->bm, n))) {
+        dfree(h->V);
+        dfree(h->Z);
+        dfree(h->w);
+        dfree(h->bm);
+        h->V = h->Z = h->w = h->bm = nullptr;
+        return rc;
+    }
+    h->m = m;
+    return HELM_OK;
+}
+
+// Flexible GMRES(m) for one right-hand side, right-preconditioned by
+// P_A-DEF1 (z_j stored), true residual at every restart.
+int solve_one(helm_ctx *h, const cd *b, cd *x, helm_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t n = h->L[0].n();
+    const int m = h->m;
+    const Lev L0 = h->lev(0);
+    const int force = h->o.force_iters;
+    const int cap = force > 0 ? force : h->o.maxit;
+    helm_solve_info inf{};
+    HCHK(launch_mask_copy(L0, b, h->bm, h->st));
+    double bnorm;
+    RCHK(vnorm(h, h->bm, n, &bnorm));
+    if (!std::isfinite(bnorm)) return HELM_ENONFINITE;
+    if (h->o.x0_given)
+        HCHK(launch_mask_copy(L0, x, x, h->st));
+    else
+        HCHK(launch_zero(x, n, h->st));
+    int rc = HELM_OK;
+    if (bnorm == 0.0) {
+        HCHK(launch_zero(x, n, h->st));
+        inf.converged = 1;
+    } else {
+        Givens gv(m);
+        std::vector<zc> col(m + 1), y;
+        for (;;) {
+            RCHK(apply_A(h, 0, x, h->bm, h->w));
+            double beta;
+            RCHK(vnorm(h, h->w, n, &beta));
+            inf.relres = beta / bnorm;
+            if (force <= 0 && inf.relres <= h->o.tol) {
+                inf.converged = 1;
+                break;
+            }
+            if (inf.outer_iters >= cap || beta == 0.0) break;
+            HCHK(launch_scale(h->w, h->hbuf + 2 * PSTRIDE, h->V, n, h->st));
+            gv.start(beta);
+            int jend = 0;
+            for (int j = 0; j < m && inf.outer_iters < cap; j++) {
+                cd *vj = h->V + (size_t)j * n, *zj = h->Z + (size_t)j * n;
+                int inner = 0;
+                RCHK(deflate_one(h, HELM_DEFL_ADEF1, vj, zj, &inner));
+                inf.inner_iters_total += inner;
+                if (inner > inf.inner_iters_max) inf.inner_iters_max = inner;
+                RCHK(apply_A(h, 0, zj, nullptr, h->w));
+                double hn;
+                RCHK(arnoldi_cgs2(h, h->V, n, j + 1, h->w, n, col.data(), &hn, 0));
+                const double res = gv.add_column(j, col.data(), hn);
+                inf.outer_iters++;
+                jend = j + 1;
+                if (std::getenv("HELMDEFL_LOG"))
+                    std::fprintf(stderr, "helmdefl: it %d  est relres %.3e  inner %d\n",
+                                 inf.outer_iters, res / bnorm, inner);
+                if (force <= 0 && res <= h->o.tol * bnorm) break;
+                if (hn == 0.0) break;
+            }
+            gv.solve(jend, y);
+            RCHK(upload_y(h, y));
+            HCHK(launch_lincomb(h->Z, n, jend, h->ydev, x, n, 1, h->st));
+            if (force > 0 && inf.outer_iters >= cap) {
+                RCHK(apply_A(h, 0, x, h->bm, h->w));
+                double r2;
+                RCHK(vnorm(h, h->w, n, &r2));
+                inf.relres = r2 / bnorm;
+                inf.converged = inf.relres <= h->o.tol;
+                break;
+            }
+        }
+        if (!inf.converged && force <= 0) rc = HELM_ENOCONV;
+    }
+    HCHK(hipStreamSynchronize(h->st));
+    inf.t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+// Dense inverse of M on the coarsest level (Gauss-Jordan, partial pivoting).
+// Non-unknown nodes get zero rows and columns, so they read and write 0.
+int setup_coarsest(helm_ctx *h, const std::vector<std::vector<double>> &khost)
+{
+    const int l = h->nlev - 1;
+    const int nx = h->L[l].nx, ny = h->L[l].ny, n = nx * ny;
+    if (n > MAX_COARSEST) return HELM_EGRID;
+    Lev Lv = make_lev(nx, ny, h->L[l].hx, h->L[l].hy, h->g.bc,
+                      khost[l].empty() ? nullptr : khost[l].data(), h->kconst);
+    std::vector<zc> A((size_t)n * n, zc(0)), B((size_t)n * n, zc(0));
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            const int p = j * nx + i;
+            B[(size_t)p * n + p] = 1.0;
+            cd ap;
+            double aw, ae, as, an;
+            if (!coef5(Lv, h->shift, i, j, ap, aw, ae, as, an)) {
+                A[(size_t)p * n + p] = 1.0;
+                continue;
+            }
+            A[(size_t)p * n + p] = zc(ap.x, ap.y);
+            if (aw != 0.0) A[(size_t)p * n + p - 1] += aw;
+            if (ae != 0.0) A[(size_t)p * n + p + 1] += ae;
+            if (as != 0.0) A[(size_t)p * n + p - nx] += as;
+            if (an != 0.0) A[(size_t)p * n + p + nx] += an;
+        }
+    for (int c = 0; c < n; c++) {
+        int piv = c;
+        double best = std::abs(A[(size_t)c * n + c]);
+        for (int r = c + 1; r < n; r++)
+            if (std::abs(A[(size_t)r * n + c]) > best) {
+                best = std::abs(A[(size_t)r * n + c]);
+                piv = r;
+            }
+        if (best == 0.0) return HELM_EGRID;  // singular coarsest operator
+        if (piv != c)
+            for (int q = 0; q < n; q++) {
+                std::swap(A[(size_t)c * n + q], A[(size_t)piv * n + q]);
+                std::swap(B[(size_t)c * n + q], B[(size_t)piv * n + q]);
+            }
+        const zc d = 1.0 / A[(size_t)c * n + c];
+        for (int q = 0; q < n; q++) {
+            A[(size_t)c * n + q] *= d;
+            B[(size_t)c * n + q] *= d;
+        }
+        for (int r = 0; r < n; r++) {
+            if (r == c) continue;
+            const zc f = A[(size_t)r * n + c];
+            if (f == 0.0) continue;
+            for (int q = 0; q < n; q++) {
+                A[(size_t)r * n + q] -= f * A[(size_t)c * n + q];
+                B[(size_t)r * n + q] -= f * B[(size_t)c * n + q];
+            }
+        }
+    }
+    std::vector<cd> inv((size_t)n * n);
+    for (int r = 0; r < n; r++)
+        for (int c = 0; c < n; c++) {
+            const bool keep = unknown(Lv, r % nx, r / nx) && unknown(Lv, c % nx, c / nx);
+            const zc v = keep ? B[(size_t)r * n + c] : zc(0);
+            inv[(size_t)r * n + c] = make_double2(v.real(), v.imag());
+        }
+    RCHK(dalloc(&h->cinv, (size_t)n * n));
+    HCHK(hipMemcpy(h->cinv, inv.data(), inv.size() * sizeof(cd), hipMemcpyHostToDevice));
+    h->ncoarsest = n;
+    return HELM_OK;
+}
+
+void release(helm_ctx *h)
+{
+    if (!h) return;
+    if (h->st) (void)hipStreamSynchronize(h->st);
+    for (int l = 0; l < h->nlev; l++) {
+        dfree(h->L[l].kdev);
+        dfree(h->L[l].r);
+        dfree(h->L[l].x);
+    }
+    dfree(h->cinv);
+    dfree(h->v1);
+    dfree(h->v2);
+    dfree(h->tf);
+    dfree(h->f1);
+    dfree(h->f2);
+    dfree(h->Vc);
+    dfree(h->wc);
+    dfree(h->zc_);
+    dfree(h->xin);
+    dfree(h->part);
+    dfree(h->hbuf);
+    dfree(h->ydev);
+    dfree(h->V);
+    dfree(h->Z);
+    dfree(h->w);
+    dfree(h->bm);
+    if (h->hpin) (void)hipHostFree(h->hpin);
+    for (auto &p : h->pend) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : h->ev_free) (void)hipEventDestroy(e);
+    delete h;
+}
+
+int create_impl(const helm_grid *g, const double *k_dev, double k_const, const helm_opts *opts,
+                void *stream, helm_ctx **out)
+{
+    if (!g || !out) return HELM_EINVAL;
+    *out = nullptr;
+    if (!(g->hx > 0) || !(g->hy > 0) || !std::isfinite(g->hx) || !std::isfinite(g->hy))
+        return HELM_EINVAL;
+    if (g->bc != HELM_BC_DIRICHLET && g->bc != HELM_BC_SOMMERFELD) return HELM_EINVAL;
+    if (!coarsenable(g->nx, g->ny)) return HELM_EGRID;
+    helm_opts o;
+    helm_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.nu_pre != 1 || o.nu_post != 1) return HELM_EINVAL;
+    if (!(o.omega > 0) || !std::isfinite(o.beta_re) || !std::isfinite(o.beta_im)) return HELM_EINVAL;
+    if (o.defl_vectors != HELM_Z_LINEAR && o.defl_vectors != HELM_Z_HIGH) return HELM_EINVAL;
+    if (o.coarse_op != HELM_COARSE_GALERKIN && o.coarse_op != HELM_COARSE_REDGLK2)
+        return HELM_EINVAL;
+    if (o.coarse_op == HELM_COARSE_REDGLK2 && g->hx != g->hy) return HELM_EINVAL;
+    if (o.coarse_mode != HELM_CMODE_FIXED && o.coarse_mode != HELM_CMODE_TOL) return HELM_EINVAL;
+    if (o.coarse_iters < 1 || o.coarse_restart < 1 || o.coarse_restart > MAX_RESTART)
+        return HELM_EINVAL;
+    if (o.restart < 1 || o.restart > MAX_RESTART || o.maxit < 1) return HELM_EINVAL;
+    if (!(o.tol >= 0) || !(o.coarse_tol >= 0)) return HELM_EINVAL;
+    if (!k_dev && (!std::isfinite(k_const) || k_const < 0)) return HELM_ENONFINITE;
+
+    helm_ctx *h = new (std::nothrow) helm_ctx();
+    if (!h) return HELM_ENOMEM;
+    h->g = *g;
+    h->o = o;
+    h->st = (hipStream_t)stream;
+    h->kconst = k_const;
+    h->shift = make_double2(o.beta_re, o.beta_im);
+    h->zho = o.defl_vectors == HELM_Z_HIGH;
+    int rc = HELM_OK;
+
+    // level dims
+    int nx = g->nx, ny = g->ny;
+    double hx = g->hx, hy = g->hy;
+    h->nlev = 0;
+    for (;;) {
+        LevelH &q = h->L[h->nlev++];
+        q.nx = nx;
+        q.ny = ny;
+        q.hx = hx;
+        q.hy = hy;
+        if (!coarsenable(nx, ny) || h->nlev == MAXLEV) break;
+        nx = (nx + 1) / 2;
+        ny = (ny + 1) / 2;
+        hx *= 2;
+        hy *= 2;
+    }
+    // wavenumber per level: copy, validate, inject
+    std::vector<std::vector<double>> kh(h->nlev);
+    if (k_dev) {
+        kh[0].resize(h->L[0].n());
+        if (hipMemcpy(kh[0].data(), k_dev, kh[0].size() * sizeof(double), hipMemcpyDeviceToHost) !=
+            hipSuccess) {
+            release(h);
+            return HELM_EHIP;
+        }
+        for (double v : kh[0])
+            if (!std::isfinite(v) || v < 0) {
+                release(h);
+                return HELM_ENONFINITE;
+            }
+        for (int l = 1; l < h->nlev; l++) {
+            kh[l].resize(h->L[l].n());
+            const int fnx = h->L[l - 1].nx;
+            for (int j = 0; j < h->L[l].ny; j++)
+                for (int i = 0; i < h->L[l].nx; i++)
+                    kh[l][(size_t)j * h->L[l].nx + i] = kh[l - 1][(size_t)(2 * j) * fnx + 2 * i];
+        }
+        for (int l = 0; l < h->nlev && !rc; l++) {
+            rc = dalloc(&h->L[l].kdev, h->L[l].n());
+            if (!rc && hipMemcpy(h->L[l].kdev, kh[l].data(), kh[l].size() * sizeof(double),
+                                 hipMemcpyHostToDevice) != hipSuccess)
+                rc = HELM_EHIP;
+        }
+    }
+    // V-cycle buffers on levels >= 1
+    for (int l = 1; l < h->nlev && !rc; l++) {
+        rc = dalloc(&h->L[l].r, h->L[l].n());
+        if (!rc) rc = dalloc(&h->L[l].x, h->L[l].n());
+    }
+    if (!rc) rc = setup_coarsest(h, kh);
+    // deflation and inner-GMRES workspace
+    const size_t nf = h->L[0].n(), nc = h->L[1].n();
+    h->mc = o.coarse_restart;
+    if (!rc) rc = dalloc(&h->v1, nc);
+    if (!rc) rc = dalloc(&h->v2, nc);
+    if (!rc) rc = dalloc(&h->tf, nf);
+    if (!rc && o.coarse_op == HELM_COARSE_GALERKIN) rc = dalloc(&h->f1, nf);
+    if (!rc && o.coarse_op == HELM_COARSE_GALERKIN) rc = dalloc(&h->f2, nf);
+    if (!rc) rc = dalloc(&h->Vc, (size_t)(h->mc + 1) * nc);
+    if (!rc) rc = dalloc(&h->wc, nc);
+    if (!rc) rc = dalloc(&h->zc_, nc);
+    if (!rc) rc = dalloc(&h->xin, nc);
+    h->part_blocks = krylov_blocks(nf);
+    if (!rc) rc = dalloc(&h->part, (size_t)h->part_blocks * PSTRIDE);
+    if (!rc) rc = dalloc(&h->hbuf, (size_t)HBUF);
+    if (!rc) rc = dalloc(&h->ydev, (size_t)PSTRIDE);
+    if (!rc && hipHostMalloc((void **)&h->hpin, HBUF * sizeof(cd)) != hipSuccess) {
+        h->hpin = nullptr;
+        rc = HELM_ENOMEM;
+    }
+    if (!rc) {
+        // slot 2*PSTRIDE+1 holds the constant 1 used to accumulate on the
+        // coarsest level
+        cd one = make_double2(1.0, 0.0);
+        if (hipMemcpy(h->hbuf + 2 * PSTRIDE + 1, &one, sizeof(cd), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            rc = HELM_EHIP;
+    }
+    if (rc) {
+        release(h);
+        return rc;
+    }
+    *out = h;
+    return HELM_OK;
+}
+
+bool valid(helm_ctx *h) { return h != nullptr; }
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+int helm_opts_default(helm_opts *o)
+{
+    if (!o) return HELM_EINVAL;
+    o->beta_re = 1.0;
+    o->beta_im = 0.5;
+    o->omega = 0.8;
+    o->nu_pre = 1;
+    o->nu_post = 1;
+    o->defl_vectors = HELM_Z_HIGH;
+    o->coarse_op = HELM_COARSE_GALERKIN;
+    o->coarse_mode = HELM_CMODE_TOL;
+    o->coarse_iters = 300;
+    o->coarse_restart = 30;
+    o->coarse_tol = 1e-1;
+    o->restart = 50;
+    o->maxit = 1000;
+    o->tol = 1e-6;
+    o->x0_given = 0;
+    o->force_iters = 0;
+    return HELM_OK;
+}
+
+int helm_create(const helm_grid *g, const double *k_dev, double k_const, const helm_opts *opts,
+                void *stream, helm_ctx **out)
+{
+    try {
+        return create_impl(g, k_dev, k_const, opts, stream, out);
+    } catch (...) {
+        return HELM_ENOMEM;
+    }
+}
+
+int helm_destroy(helm_ctx *h)
+{
+    if (!h) return HELM_EINVAL;
+    release(h);
+    return HELM_OK;
+}
+
+int helm_apply(helm_ctx *h, const void *x, void *y, int nrhs)
+{
+    if (!valid(h) || !x || !y || nrhs < 1) return HELM_EINVAL;
+    const size_t n = h->L[0].n();
+    for (int r = 0; r < nrhs; r++)
+        RCHK(apply_A(h, 0, (const cd *)x + r * n, nullptr, (cd *)y + r * n));
+    return HELM_OK;
+}
+
+int cslp_vcycle(helm_ctx *h, const void *r, void *z, int nrhs)
+{
+    if (!valid(h) || !r || !z || nrhs < 1) return HELM_EINVAL;
+    const size_t n = h->L[0].n();
+    for (int q = 0; q < nrhs; q++)
+        RCHK(vcycle(h, 0, (const cd *)r + q * n, (cd *)z + q * n, 0, nullptr));
+    return HELM_OK;
+}
+
+int deflate_apply(helm_ctx *h, int mode, const void *v, void *w, int nrhs)
+{
+    if (!valid(h) || !v || !w || nrhs < 1) return HELM_EINVAL;
+    if (mode != HELM_DEFL_Q && mode != HELM_DEFL_P && mode != HELM_DEFL_ADEF1) return HELM_EINVAL;
+    const size_t n = h->L[0].n();
+    try {
+        for (int q = 0; q < nrhs; q++)
+            RCHK(deflate_one(h, mode, (const cd *)v + q * n, (cd *)w + q * n, nullptr));
+    } catch (...) {
+        return HELM_ENOMEM;
+    }
+    return HELM_OK;
+}
+
+int helm_solve(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *info)
+{
+    if (!valid(h) || !b || !x || nrhs < 1) return HELM_EINVAL;
+    const size_t n = h->L[0].n();
+    int worst = HELM_OK;
+    try {
+        RCHK(ensure_outer(h));
+        for (int q = 0; q < nrhs; q++) {
+            const int rc = solve_one(h, (const cd *)b + q * n, (cd *)x + q * n,
+                                     info ? info + q : nullptr);
+            if (rc != HELM_OK && rc != HELM_ENOCONV) return rc;
+            if (rc == HELM_ENOCONV) worst = rc;
+        }
+    } catch (...) {
+        return HELM_ENOMEM;
+    }
+    return worst;
+}
+
+const char *helm_strerror(int code)
+{
+    switch (code) {
+    case HELM_OK: return "success";
+    case HELM_EINVAL: return "invalid argument";
+    case HELM_EGRID: return "grid cannot be coarsened (need odd nx, ny >= 5)";
+    case HELM_ENONFINITE: return "non-finite value in k or right-hand side";
+    case HELM_ENOMEM: return "out of memory";
+    case HELM_EHIP: return "HIP runtime error";
+    case HELM_ENOCONV: return "no convergence within maxit";
+    default: return "unknown error";
+    }
+}
+
+int helm_coarse_dims(helm_ctx *h, int *nxc, int *nyc)
+{
+    if (!valid(h) || !nxc || !nyc) return HELM_EINVAL;
+    *nxc = h->L[1].nx;
+    *nyc = h->L[1].ny;
+    return HELM_OK;
+}
+
+int helm_num_levels(helm_ctx *h, int *nlev)
+{
+    if (!valid(h) || !nlev) return HELM_EINVAL;
+    *nlev = h->nlev;
+    return HELM_OK;
+}
+
+int helm_level_dims(helm_ctx *h, int l, int *nx, int *ny)
+{
+    if (!valid(h) || !nx || !ny || l < 0 || l >= h->nlev) return HELM_EINVAL;
+    *nx = h->L[l].nx;
+    *ny = h->L[l].ny;
+    return HELM_OK;
+}
+
+int helm_z_restrict(helm_ctx *h, const void *vf, void *vc)
+{
+    if (!valid(h) || !vf || !vc) return HELM_EINVAL;
+    HCHK(launch_zt(h->lev(0), h->lev(1), h->zho, (const cd *)vf, nullptr, (cd *)vc, h->st));
+    return HELM_OK;
+}
+
+int helm_z_prolong(helm_ctx *h, const void *vc, void *vf)
+{
+    if (!valid(h) || !vf || !vc) return HELM_EINVAL;
+    HCHK(launch_z(h->lev(0), h->lev(1), h->zho, (const cd *)vc, (cd *)vf, h->st));
+    return HELM_OK;
+}
+
+int helm_coarse_apply(helm_ctx *h, const void *x, void *y)
+{
+    if (!valid(h) || !x || !y) return HELM_EINVAL;
+    return coarse_apply(h, (const cd *)x, nullptr, (cd *)y);
+}
+
+int helm_coarse_solve(helm_ctx *h, const void *v1, void *v2, int *iters)
+{
+    if (!valid(h) || !v1 || !v2) return HELM_EINVAL;
+    try {
+        RCHK(coarse_solve(h, (const cd *)v1, (cd *)v2, iters));
+    } catch (...) {
+        return HELM_ENOMEM;
+    }
+    HCHK(hipStreamSynchronize(h->st));
+    return HELM_OK;
+}
+
+int helm_timing_enable(helm_ctx *h, int kclass, int level)
+{
+    if (!valid(h) || kclass >= HELM_K_NCLASSES) return HELM_EINVAL;
+    RCHK(timing_flush(h));
+    h->t_cls = kclass < 0 ? -1 : kclass;
+    h->t_lev = level;
+    h->t_count = 0;
+    h->t_ms = 0;
+    h->t_bytes = 0;
+    return HELM_OK;
+}
+
+int helm_timing_read(helm_ctx *h, long long *launches, double *total_ms, double *alg_bytes)
+{
+    if (!valid(h)) return HELM_EINVAL;
+    RCHK(timing_flush(h));
+    if (launches) *launches = h->t_count;
+    if (total_ms) *total_ms = h->t_ms;
+    if (alg_bytes) *alg_bytes = h->t_bytes;
+    return HELM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,893 @@
+// kernels.hip -- HIP kernels for gfx950 (MI355X, wave64) of the matrix-free
+// two-level deflation Helmholtz solver (arXiv 2308.06152).
+//
+// Every kernel here is bandwidth-bound (<= ~4 flop/byte in FP64), so none uses
+// MFMA.  Design rules:
+//  * complex128 is one 16-byte load/store per node (double2), rows are
+//    contiguous in x so a wave touches 1 KB of consecutive memory per row;
+//  * stencil kernels stage a tile plus halo in LDS and fuse the steps of the
+//    method that share the tile (smoothing + residual + restriction in one
+//    pass, interpolation + correction + smoothing in another);
+//  * the block -> tile map is XCD-aware: consecutive block ids go to different
+//    XCDs, so tiles are renumbered to give every XCD a contiguous band of the
+//    grid, keeping vertical halos in that XCD's L2;
+//  * reductions are deterministic: fixed per-block partial sums, then a fixed
+//    tree in a second kernel.
+#include "hd_common.h"
+
+namespace hd {
+
+#define HD_LAUNCH_CHECK() return hipGetLastError()
+
+// ------------------------------------------------------------------------
+// small complex helpers
+// ------------------------------------------------------------------------
+__device__ __forceinline__ cd czero() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cd csub(cd a, cd b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cd cscal(double s, cd a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ cd cmul(cd a, cd b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ cd cinv(cd a)
+{
+    const double d = 1.0 / (a.x * a.x + a.y * a.y);
+    return make_double2(a.x * d, -a.y * d);
+}
+// a += s * b  (s real)
+__device__ __forceinline__ void caxpy(cd &a, double s, cd b)
+{
+    a.x = fma(s, b.x, a.x);
+    a.y = fma(s, b.y, a.y);
+}
+
+// Map hardware block id to a logical tile id so that each of the 8 XCDs
+// (which receive block ids round-robin) works on a contiguous range of tiles.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int X = 8;
+    const int xcd = b % X, q = b / X, full = nb / X, rem = nb % X;
+    return xcd < rem ? xcd * (full + 1) + q : rem * (full + 1) + (xcd - rem) * full + q;
+}
+
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// 1D interpolation rule from the coarse grid to fine index i: returns the
+// number of coarse neighbours and fills their indices and weights.
+// zho = 1: Bezier vectors (even i: (1, 6, 1)/8 on I-1, I, I+1; odd: 1/2, 1/2);
+// zho = 0: linear (even i: 1 on I; odd: 1/2, 1/2).
+__device__ __forceinline__ int zrule(int i, int zho, int *I, double *w)
+{
+    if (i & 1) {
+        I[0] = (i - 1) >> 1;
+        I[1] = (i + 1) >> 1;
+        w[0] = 0.5;
+        w[1] = 0.5;
+        return 2;
+    }
+    if (zho) {
+        I[0] = (i >> 1) - 1;
+        I[1] = i >> 1;
+        I[2] = (i >> 1) + 1;
+        w[0] = 0.125;
+        w[1] = 0.75;
+        w[2] = 0.125;
+        return 3;
+    }
+    I[0] = i >> 1;
+    w[0] = 1.0;
+    return 1;
+}
+
+// (I_{2h}^h vc) at fine node (i,j); coarse nodes outside the grid or not
+// unknowns contribute nothing.
+__device__ __forceinline__ cd prolong_at(const Lev &Lc, const cd *__restrict__ vc, int i, int j,
+                                         int zho)
+{
+    int Ix[3], Jy[3];
+    double wx[3], wy[3];
+    const int nxw = zrule(i, zho, Ix, wx), nyw = zrule(j, zho, Jy, wy);
+    cd s = czero();
+    for (int b = 0; b < nyw; b++) {
+        const int J = Jy[b];
+        if (J < 0 || J >= Lc.ny) continue;
+        for (int a = 0; a < nxw; a++) {
+            const int I = Ix[a];
+            if (I < 0 || I >= Lc.nx || !unknown(Lc, I, J)) continue;
+            caxpy(s, wx[a] * wy[b], vc[(size_t)J * Lc.nx + I]);
+        }
+    }
+    return s;
+}
+
+// ------------------------------------------------------------------------
+// 5-point operator: y = op x  or  y = b - op x
+// Block: 64 x 4 threads; each thread owns one column of a 64 x 16 tile and
+// streams 4 rows, keeping south/centre/north in registers.
+// ------------------------------------------------------------------------
+constexpr int AP_TX = 64, AP_TY = 16, AP_RPT = 4;
+
+template <bool RESID>
+__global__ __launch_bounds__(256) void k_apply5(Lev L, cd s, const cd *__restrict__ x,
+                                                const cd *__restrict__ b, cd *__restrict__ y,
+                                                int tiles_x)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int i = (t % tiles_x) * AP_TX + (threadIdx.x & 63);
+    const int j0 = (t / tiles_x) * AP_TY + (threadIdx.x >> 6) * AP_RPT;
+    if (i >= L.nx || j0 >= L.ny) return;
+    const int nx = L.nx;
+    cd xs = (j0 > 0) ? x[(size_t)(j0 - 1) * nx + i] : czero();
+    cd xc = x[(size_t)j0 * nx + i];
+#pragma unroll
+    for (int r = 0; r < AP_RPT; r++) {
+        const int j = j0 + r;
+        if (j >= L.ny) break;
+        const size_t p = (size_t)j * nx + i;
+        const cd xn = (j + 1 < L.ny) ? x[p + nx] : czero();
+        cd ap;
+        double aw, ae, as, an;
+        cd v = czero();
+        if (coef5(L, s, i, j, ap, aw, ae, as, an)) {
+            v = cmul(ap, xc);
+            if (aw != 0.0) caxpy(v, aw, x[p - 1]);
+            if (ae != 0.0) caxpy(v, ae, x[p + 1]);
+            if (as != 0.0) caxpy(v, as, xs);
+            if (an != 0.0) caxpy(v, an, xn);
+            if (RESID) v = csub(b[p], v);
+        }
+        y[p] = v;
+        xs = xc;
+        xc = xn;
+    }
+}
+
+hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hipStream_t st)
+{
+    const int tx = cdiv(L.nx, AP_TX), ty = cdiv(L.ny, AP_TY);
+    if (b)
+        k_apply5<true><<<tx * ty, 256, 0, st>>>(L, s, x, b, y, tx);
+    else
+        k_apply5<false><<<tx * ty, 256, 0, st>>>(L, s, x, b, y, tx);
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
+// V-cycle, downward pass on a level (fused):
+//   x1 = omega D^{-1} r            (one damped-Jacobi sweep from x = 0)
+//   r1 = r - M x1                  (residual)
+//   rc = full weighting of r1      (1/16 [1 2 1; 2 4 2; 1 2 1], truncated)
+// One block computes a 32 x 8 tile of coarse nodes; x1 lives in LDS on the
+// 67 x 19 fine region it needs, r1 on the inner 65 x 17 region.
+// ------------------------------------------------------------------------
+constexpr int VD_CX = 32, VD_CY = 8;
+constexpr int VD_X1W = 2 * VD_CX + 3, VD_X1H = 2 * VD_CY + 3;  // 67 x 19
+constexpr int VD_R1W = 2 * VD_CX + 1, VD_R1H = 2 * VD_CY + 1;  // 65 x 17
+
+__global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double omega,
+                                                 const cd *__restrict__ r, cd *__restrict__ rc,
+                                                 int tiles_x)
+{
+    __shared__ cd sx1[VD_X1H][VD_X1W];
+    __shared__ cd sr1[VD_R1H][VD_R1W];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int I0 = (t % tiles_x) * VD_CX, J0 = (t / tiles_x) * VD_CY;
+    const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
+    for (int q = threadIdx.x; q < VD_X1W * VD_X1H; q += 256) {
+        const int a = q % VD_X1W, bb = q / VD_X1W;
+        const int fi = fi0 + a, fj = fj0 + bb;
+        cd v = czero();
+        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
+            cd ap;
+            double aw, ae, as, an;
+            if (coef5(Lf, s, fi, fj, ap, aw, ae, as, an))
+                v = cscal(omega, cmul(cinv(ap), r[(size_t)fj * Lf.nx + fi]));
+        }
+        sx1[bb][a] = v;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < VD_R1W * VD_R1H; q += 256) {
+        const int a = q % VD_R1W, bb = q / VD_R1W;
+        const int fi = fi0 + 1 + a, fj = fj0 + 1 + bb;
+        cd v = czero();
+        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
+            cd ap;
+            double aw, ae, as, an;
+            if (coef5(Lf, s, fi, fj, ap, aw, ae, as, an)) {
+                cd m = cmul(ap, sx1[bb + 1][a + 1]);
+                caxpy(m, aw, sx1[bb + 1][a]);
+                caxpy(m, ae, sx1[bb + 1][a + 2]);
+                caxpy(m, as, sx1[bb][a + 1]);
+                caxpy(m, an, sx1[bb + 2][a + 1]);
+                v = csub(r[(size_t)fj * Lf.nx + fi], m);
+            }
+        }
+        sr1[bb][a] = v;
+    }
+    __syncthreads();
+    const int I = I0 + (threadIdx.x % VD_CX), J = J0 + (threadIdx.x / VD_CX);
+    if (I >= Lc.nx || J >= Lc.ny) return;
+    cd v = czero();
+    if (unknown(Lc, I, J)) {
+        const int a = 2 * (I - I0) + 1, bb = 2 * (J - J0) + 1;
+        cd c = cscal(4.0, sr1[bb][a]);
+        cd e = cadd(cadd(sr1[bb][a - 1], sr1[bb][a + 1]), cadd(sr1[bb - 1][a], sr1[bb + 1][a]));
+        cd d = cadd(cadd(sr1[bb - 1][a - 1], sr1[bb - 1][a + 1]),
+                    cadd(sr1[bb + 1][a - 1], sr1[bb + 1][a + 1]));
+        v = cscal(1.0 / 16.0, cadd(cadd(c, cscal(2.0, e)), d));
+    }
+    rc[(size_t)J * Lc.nx + I] = v;
+}
+
+hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r, cd *rc,
+                          hipStream_t st)
+{
+    const int tx = cdiv(Lc.nx, VD_CX), ty = cdiv(Lc.ny, VD_CY);
+    k_vc_down<<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, r, rc, tx);
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
+// V-cycle, upward pass on a level (fused):
+//   x2 = omega D^{-1} r + P ec      (the pre-smoothed iterate, recomputed,
+//                                    plus the bilinear coarse correction)
+//   x3 = x2 + omega D^{-1} (r - M x2)   (post-smoothing sweep)
+//   out = x3 [+ Z v2] [+ out]
+// One block writes a 64 x 16 fine tile; x2 lives in LDS on 66 x 18.
+// ------------------------------------------------------------------------
+constexpr int VU_TX = 64, VU_TY = 16;
+constexpr int VU_W = VU_TX + 2, VU_H = VU_TY + 2;
+
+__global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omega,
+                                               const cd *__restrict__ r,
+                                               const cd *__restrict__ ec, cd *__restrict__ out,
+                                               int accumulate, const cd *__restrict__ v2,
+                                               int zho, int tiles_x)
+{
+    __shared__ cd sx2[VU_H][VU_W];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int i0 = (t % tiles_x) * VU_TX, j0 = (t / tiles_x) * VU_TY;
+    for (int q = threadIdx.x; q < VU_W * VU_H; q += 256) {
+        const int a = q % VU_W, bb = q / VU_W;
+        const int fi = i0 - 1 + a, fj = j0 - 1 + bb;
+        cd v = czero();
+        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
+            cd ap;
+            double aw, ae, as, an;
+            if (coef5(Lf, s, fi, fj, ap, aw, ae, as, an)) {
+                v = cscal(omega, cmul(cinv(ap), r[(size_t)fj * Lf.nx + fi]));
+                v = cadd(v, prolong_at(Lc, ec, fi, fj, 0));
+            }
+        }
+        sx2[bb][a] = v;
+    }
+    __syncthreads();
+    const int i = i0 + (threadIdx.x & 63);
+    if (i >= Lf.nx) return;
+#pragma unroll
+    for (int rr = 0; rr < VU_TY / 4; rr++) {
+        const int jl = (threadIdx.x >> 6) * (VU_TY / 4) + rr;
+        const int j = j0 + jl;
+        if (j >= Lf.ny) break;
+        const int a = i - i0 + 1, bb = jl + 1;
+        const size_t p = (size_t)j * Lf.nx + i;
+        cd ap;
+        double aw, ae, as, an;
+        cd v = czero();
+        if (coef5(Lf, s, i, j, ap, aw, ae, as, an)) {
+            cd m = cmul(ap, sx2[bb][a]);
+            caxpy(m, aw, sx2[bb][a - 1]);
+            caxpy(m, ae, sx2[bb][a + 1]);
+            caxpy(m, as, sx2[bb - 1][a]);
+            caxpy(m, an, sx2[bb + 1][a]);
+            v = cadd(sx2[bb][a], cscal(omega, cmul(cinv(ap), csub(r[p], m))));
+            if (v2) v = cadd(v, prolong_at(Lc, v2, i, j, zho));
+        }
+        if (accumulate) v = cadd(v, out[p]);
+        out[p] = v;
+    }
+}
+
+hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
+                        const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
+                        hipStream_t st)
+{
+    const int tx = cdiv(Lf.nx, VU_TX), ty = cdiv(Lf.ny, VU_TY);
+    k_vc_up<<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, r, ec, out, accumulate, v2, zho, tx);
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
+// Coarsest level: x = Minv r (dense precomputed inverse, one row per thread)
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_coarsest(int n, const cd *__restrict__ Minv,
+                                                  const cd *__restrict__ r, cd *__restrict__ x)
+{
+    const int row = blockIdx.x * 256 + threadIdx.x;
+    if (row >= n) return;
+    cd s = czero();
+    const cd *m = Minv + (size_t)row * n;
+    for (int c = 0; c < n; c++) s = cadd(s, cmul(m[c], r[c]));
+    x[row] = s;
+}
+
+hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st)
+{
+    k_coarsest<<<cdiv(n, 256), 256, 0, st>>>(n, Minv, r, x);
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
+// Deflation restriction vc = Z^T vf (or b - Z^T vf): [1 4 6 4 1]/8 (Bezier)
+// or 1/2 [1 2 1] (linear) per axis, centred on fine node (2I, 2J).  One block
+// computes a 32 x 8 coarse tile from a 67 x 19 fine LDS tile; the x pass is
+// done first into LDS, then the y pass.
+// ------------------------------------------------------------------------
+constexpr int ZT_CX = 32, ZT_CY = 8;
+constexpr int ZT_W = 2 * ZT_CX + 3, ZT_H = 2 * ZT_CY + 3;
+
+template <bool RESID>
+__global__ __launch_bounds__(256) void k_zt(Lev Lf, Lev Lc, int zho, const cd *__restrict__ vf,
+                                            const cd *__restrict__ b, cd *__restrict__ vc,
+                                            int tiles_x)
+{
+    __shared__ cd sv[ZT_H][ZT_W];
+    __shared__ cd sx[ZT_H][ZT_CX];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int I0 = (t % tiles_x) * ZT_CX, J0 = (t / tiles_x) * ZT_CY;
+    const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
+    for (int q = threadIdx.x; q < ZT_W * ZT_H; q += 256) {
+        const int a = q % ZT_W, bb = q / ZT_W;
+        const int fi = fi0 + a, fj = fj0 + bb;
+        cd v = czero();
+        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny && unknown(Lf, fi, fj))
+            v = vf[(size_t)fj * Lf.nx + fi];
+        sv[bb][a] = v;
+    }
+    __syncthreads();
+    const double w0 = zho ? 0.75 : 1.0, w1 = 0.5, w2 = zho ? 0.125 : 0.0;
+    for (int q = threadIdx.x; q < ZT_CX * ZT_H; q += 256) {
+        const int c = q % ZT_CX, bb = q / ZT_CX;
+        const int a = 2 * c + 2;
+        cd v = cscal(w0, sv[bb][a]);
+        caxpy(v, w1, cadd(sv[bb][a - 1], sv[bb][a + 1]));
+        if (zho) caxpy(v, w2, cadd(sv[bb][a - 2], sv[bb][a + 2]));
+        sx[bb][c] = v;
+    }
+    __syncthreads();
+    const int c = threadIdx.x % ZT_CX, rl = threadIdx.x / ZT_CX;
+    const int I = I0 + c, J = J0 + rl;
+    if (I >= Lc.nx || J >= Lc.ny) return;
+    cd v = czero();
+    if (unknown(Lc, I, J)) {
+        const int bb = 2 * rl + 2;
+        v = cscal(w0, sx[bb][c]);
+        caxpy(v, w1, cadd(sx[bb - 1][c], sx[bb + 1][c]));
+        if (zho) caxpy(v, w2, cadd(sx[bb - 2][c], sx[bb + 2][c]));
+        if (RESID) v = csub(b[(size_t)J * Lc.nx + I], v);
+    }
+    vc[(size_t)J * Lc.nx + I] = v;
+}
+
+hipError_t launch_zt(const Lev &Lf, const Lev &Lc, int zho, const cd *vf, const cd *b, cd *vc,
+                     hipStream_t st)
+{
+    const int tx = cdiv(Lc.nx, ZT_CX), ty = cdiv(Lc.ny, ZT_CY);
+    if (b)
+        k_zt<true><<<tx * ty, 256, 0, st>>>(Lf, Lc, zho, vf, b, vc, tx);
+    else
+        k_zt<false><<<tx * ty, 256, 0, st>>>(Lf, Lc, zho, vf, b, vc, tx);
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
+// Deflation prolongation vf = Z vc (thread per fine node, 64 x 4 blocks).
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_z(Lev Lf, Lev Lc, int zho, const cd *__restrict__ vc,
+                                           cd *__restrict__ vf, int tiles_x)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int i = (t % tiles_x) * 64 + (threadIdx.x & 63);
+    const int j = (t / tiles_x) * 4 + (threadIdx.x >> 6);
+    if (i >= Lf.nx || j >= Lf.ny) return;
+    cd v = czero();
+    if (unknown(Lf, i, j)) v = prolong_at(Lc, vc, i, j, zho);
+    vf[(size_t)j * Lf.nx + i] = v;
+}
+
+hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf, hipStream_t st)
+{
+    const int tx = cdiv(Lf.nx, 64), ty = cdiv(Lf.ny, 4);
+    k_z<<<tx * ty, 256, 0, st>>>(Lf, Lc, zho, vc, vf, tx);
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
+// Deflated residual t = v - A_h (Z v2), with Z v2 staged in LDS (66 x 18) and
+// never written to memory.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dresid(Lev Lf, Lev Lc, int zho,
+                                                const cd *__restrict__ v,
+                                                const cd *__restrict__ v2, cd *__restrict__ tout,
+                                                int tiles_x)
+{
+    __shared__ cd sz[VU_H][VU_W];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int i0 = (t % tiles_x) * VU_TX, j0 = (t / tiles_x) * VU_TY;
+    for (int q = threadIdx.x; q < VU_W * VU_H; q += 256) {
+        const int a = q % VU_W, bb = q / VU_W;
+        const int fi = i0 - 1 + a, fj = j0 - 1 + bb;
+        cd z = czero();
+        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny && unknown(Lf, fi, fj))
+            z = prolong_at(Lc, v2, fi, fj, zho);
+        sz[bb][a] = z;
+    }
+    __syncthreads();
+    const int i = i0 + (threadIdx.x & 63);
+    if (i >= Lf.nx) return;
+    const cd one = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int rr = 0; rr < VU_TY / 4; rr++) {
+        const int jl = (threadIdx.x >> 6) * (VU_TY / 4) + rr;
+        const int j = j0 + jl;
+        if (j >= Lf.ny) break;
+        const int a = i - i0 + 1, bb = jl + 1;
+        const size_t p = (size_t)j * Lf.nx + i;
+        cd ap;
+        double aw, ae, as, an;
+        cd o = czero();
+        if (coef5(Lf, one, i, j, ap, aw, ae, as, an)) {
+            cd m = cmul(ap, sz[bb][a]);
+            caxpy(m, aw, sz[bb][a - 1]);
+            caxpy(m, ae, sz[bb][a + 1]);
+            caxpy(m, as, sz[bb - 1][a]);
+            caxpy(m, an, sz[bb + 1][a]);
+            o = csub(v[p], m);
+        }
+        tout[p] = o;
+    }
+}
+
+hipError_t launch_dresid(const Lev &Lf, const Lev &Lc, int zho, const cd *v, const cd *v2,
+                         cd *t, hipStream_t st)
+{
+    const int tx = cdiv(Lf.nx, VU_TX), ty = cdiv(Lf.ny, VU_TY);
+    k_dresid<<<tx * ty, 256, 0, st>>>(Lf, Lc, zho, v, v2, t, tx);
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
+// ReD-Glk2 coarse operator (Section 5.2.4).
+// Interior nodes (2 <= I <= nx-3, 2 <= J <= ny-3) take the Galerkin 5x5
+// stencils, written as tensor products of 1D factors:
+//   Laplacian  = (1/H^2) [LX (x) WY + WX (x) LY],
+//                LX = LY = [-6 -8 28 -8 -6]/16,  WX = WY = [1 28 70 28 1]/64,
+//   (1D Galerkin products of the Bezier vectors with [-1 2 -1]/h^2 and with
+//   the identity, H = 2h);
+//   k^2 part   = WX (x) WY applied to (k^2 u), k taken at each stencil node;
+// these reproduce the printed stencils (1/256)[...]/(2h)^2 and k^2/64^2 [...].
+// Each thread streams one column over 16 rows, keeping the x-filtered rows in
+// registers.  Boundary rows are done by k_redglk2_band.
+// ------------------------------------------------------------------------
+__constant__ double c_L1[5] = {-6.0 / 16, -8.0 / 16, 28.0 / 16, -8.0 / 16, -6.0 / 16};
+__constant__ double c_W1[5] = {1.0 / 64, 28.0 / 64, 70.0 / 64, 28.0 / 64, 1.0 / 64};
+
+constexpr int RG_TX = 64, RG_RPW = 16;  // 64 columns x (4 waves x 16 rows)
+
+template <bool RESID, bool VARK>
+__global__ __launch_bounds__(256) void k_redglk2_int(Lev L, const cd *__restrict__ u,
+                                                     const cd *__restrict__ b,
+                                                     cd *__restrict__ y, int tiles_x)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int I = (t % tiles_x) * RG_TX + (threadIdx.x & 63);
+    const int J0 = (t / tiles_x) * (4 * RG_RPW) + (threadIdx.x >> 6) * RG_RPW;
+    if (I < 2 || I > L.nx - 3) return;
+    if (J0 > L.ny - 3) return;
+    const double iH2 = L.ihx2;  // hx == hy on this path
+    const int nx = L.nx;
+    const bool dir = L.bc == BC_DIR;
+    // rolling window of x-filtered rows: P = (LX/H^2 - k^2 WX) u  (constant k)
+    //                                    or LX/H^2 u  (variable k, with R = WX (k^2 u)),
+    //                                    Q = WX u / H^2
+    cd P[5], Q[5], R[5];
+    const double kc2 = L.kc * L.kc;
+#pragma unroll
+    for (int q = 0; q < RG_RPW + 4; q++) {
+        const int jj = J0 - 2 + q;
+        cd pv = czero(), qv = czero(), rv = czero();
+        // Dirichlet boundary rows/columns are not unknowns: read as zero
+        const bool rowok = jj >= 0 && jj < L.ny && (!dir || (jj > 0 && jj < L.ny - 1));
+        if (rowok) {
+            const cd *row = u + (size_t)jj * nx + I;
+#pragma unroll
+            for (int d = 0; d < 5; d++) {
+                const int ii = I + d - 2;
+                const cd uv = (dir && (ii == 0 || ii == nx - 1)) ? czero() : row[d - 2];
+                if (VARK) {
+                    caxpy(pv, c_L1[d] * iH2, uv);
+                    const double kk = L.k[(size_t)jj * nx + I + d - 2];
+                    caxpy(rv, c_W1[d] * kk * kk, uv);
+                } else {
+                    caxpy(pv, c_L1[d] * iH2 - kc2 * c_W1[d], uv);
+                }
+                caxpy(qv, c_W1[d] * iH2, uv);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 4; d++) {
+            P[d] = P[d + 1];
+            Q[d] = Q[d + 1];
+            if (VARK) R[d] = R[d + 1];
+        }
+        P[4] = pv;
+        Q[4] = qv;
+        if (VARK) R[4] = rv;
+        if (q >= 4) {
+            const int J = jj - 2;
+            if (J >= 2 && J <= L.ny - 3) {
+                cd o = czero();
+#pragma unroll
+                for (int d = 0; d < 5; d++) {
+                    caxpy(o, c_W1[d], P[d]);
+                    caxpy(o, c_L1[d], Q[d]);
+                    if (VARK) caxpy(o, -c_W1[d], R[d]);
+                }
+                const size_t p = (size_t)J * nx + I;
+                if (RESID) o = csub(b[p], o);
+                y[p] = o;
+            }
+        }
+    }
+}
+
+// The 5x5 printed-stencil weight at offset (dI, dJ): Laplacian / H^2 part and
+// the k^2 part.
+__device__ __forceinline__ double glk_lap(int dI, int dJ, double iH2)
+{
+    return (c_L1[dI + 2] * c_W1[dJ + 2] + c_W1[dI + 2] * c_L1[dJ + 2]) * iH2;
+}
+__device__ __forceinline__ double glk_k2w(int dI, int dJ) { return c_W1[dI + 2] * c_W1[dJ + 2]; }
+
+// value of grid node (I,J), 0 for non-unknowns
+__device__ __forceinline__ cd uat(const Lev &L, const cd *u, int I, int J)
+{
+    return unknown(L, I, J) ? u[(size_t)J * L.nx + I] : czero();
+}
+
+// Ghost value beyond the x-boundary in row J (Ig = -1 or nx): Sommerfeld
+// u_g = u_inward + 2 i H k_bnd u_bnd; Dirichlet u_g = 2 u_bnd - u_inward.
+__device__ __forceinline__ cd ghost_x(const Lev &L, const cd *u, int Ig, int J)
+{
+    const int Ib = Ig < 0 ? 0 : L.nx - 1, Ii = Ig < 0 ? 1 : L.nx - 2;
+    const cd ub = uat(L, u, Ib, J), ui = uat(L, u, Ii, J);
+    if (L.bc == BC_SOM) {
+        const double c = 2.0 * L.hx * kat(L, Ib, J);
+        return make_double2(ui.x - c * ub.y, ui.y + c * ub.x);
+    }
+    return make_double2(2.0 * ub.x - ui.x, 2.0 * ub.y - ui.y);
+}
+__device__ __forceinline__ cd ghost_y(const Lev &L, const cd *u, int I, int Jg)
+{
+    const int Jb = Jg < 0 ? 0 : L.ny - 1, Ji = Jg < 0 ? 1 : L.ny - 2;
+    const cd ub = uat(L, u, I, Jb), ui = uat(L, u, I, Ji);
+    if (L.bc == BC_SOM) {
+        const double c = 2.0 * L.hy * kat(L, I, Jb);
+        return make_double2(ui.x - c * ub.y, ui.y + c * ub.x);
+    }
+    return make_double2(2.0 * ub.x - ui.x, 2.0 * ub.y - ui.y);
+}
+
+// Boundary band of ReD-Glk2: first layer (boundary nodes) = 4 x the 5-point
+// second-order operator at spacing H with the Sommerfeld closure; second layer
+// = the 5x5 stencil with ghost nodes eliminated (k = 0 at ghosts; a ghost
+// outside in both directions is the mean of its two single-direction
+// neighbours).  Dirichlet boundary nodes are not unknowns.
+template <bool RESID>
+// Band layout: nR boundary-band rows (0, 1, ny-2, ny-1 without repeats; all
+// rows when ny < 5) cover every column; then nC band columns cover the rows
+// 2..ny-3 in between.  Band row k is k for k < 2, else ny - nR + k (columns
+// alike).
+__global__ __launch_bounds__(256) void k_redglk2_band(Lev L, const cd *__restrict__ u,
+                                                      const cd *__restrict__ b,
+                                                      cd *__restrict__ y, int nR, int nC,
+                                                      int count)
+{
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= count) return;
+    int I, J;
+    if (idx < nR * L.nx) {
+        const int k = idx / L.nx;
+        J = k < 2 ? k : L.ny - nR + k;
+        I = idx - k * L.nx;
+    } else {
+        const int q = idx - nR * L.nx;
+        const int c = q % nC;
+        I = c < 2 ? c : L.nx - nC + c;
+        J = 2 + q / nC;
+    }
+    const size_t p = (size_t)J * L.nx + I;
+    cd o = czero();
+    if (unknown(L, I, J)) {
+        const bool bnd = I == 0 || J == 0 || I == L.nx - 1 || J == L.ny - 1;
+        if (bnd) {
+            cd ap;
+            double aw, ae, as, an;
+            coef5(L, make_double2(1.0, 0.0), I, J, ap, aw, ae, as, an);
+            o = cmul(ap, u[p]);
+            if (aw != 0.0) caxpy(o, aw, u[p - 1]);
+            if (ae != 0.0) caxpy(o, ae, u[p + 1]);
+            if (as != 0.0) caxpy(o, as, u[p - L.nx]);
+            if (an != 0.0) caxpy(o, an, u[p + L.nx]);
+            o = cscal(4.0, o);
+        } else {
+            const double iH2 = L.ihx2;
+            for (int dJ = -2; dJ <= 2; dJ++)
+                for (int dI = -2; dI <= 2; dI++) {
+                    const int Ii = I + dI, Jj = J + dJ;
+                    const double lw = glk_lap(dI, dJ, iH2);
+                    const bool inx = Ii >= 0 && Ii < L.nx, iny = Jj >= 0 && Jj < L.ny;
+                    if (inx && iny) {
+                        const double kk = kat(L, Ii, Jj);
+                        caxpy(o, lw - glk_k2w(dI, dJ) * kk * kk, uat(L, u, Ii, Jj));
+                    } else if (!inx && iny) {
+                        caxpy(o, lw, ghost_x(L, u, Ii, Jj));
+                    } else if (inx && !iny) {
+                        caxpy(o, lw, ghost_y(L, u, Ii, Jj));
+                    } else {
+                        const int In = Ii < 0 ? 0 : L.nx - 1, Jn = Jj < 0 ? 0 : L.ny - 1;
+                        const cd g = cadd(ghost_y(L, u, In, Jj), ghost_x(L, u, Ii, Jn));
+                        caxpy(o, 0.5 * lw, g);
+                    }
+                }
+        }
+        if (RESID) o = csub(b[p], o);
+    }
+    y[p] = o;
+}
+
+hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, hipStream_t st)
+{
+    // interior
+    if (L.nx >= 5 && L.ny >= 5) {
+        const int tx = cdiv(L.nx, RG_TX), ty = cdiv(L.ny, 4 * RG_RPW);
+        const int nb = tx * ty;
+        if (L.k) {
+            if (b)
+                k_redglk2_int<true, true><<<nb, 256, 0, st>>>(L, x, b, y, tx);
+            else
+                k_redglk2_int<false, true><<<nb, 256, 0, st>>>(L, x, b, y, tx);
+        } else {
+            if (b)
+                k_redglk2_int<true, false><<<nb, 256, 0, st>>>(L, x, b, y, tx);
+            else
+                k_redglk2_int<false, false><<<nb, 256, 0, st>>>(L, x, b, y, tx);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // band: rows {0,1,ny-2,ny-1} and columns {0,1,nx-2,nx-1} without repeats
+    const int nR = L.ny < 4 ? L.ny : 4, nC = L.nx < 4 ? L.nx : 4;
+    const int inner_rows = L.ny - nR;  // rows 2..ny-3 when ny >= 5, else 0
+    const int count = nR * L.nx + nC * inner_rows;
+    if (b)
+        k_redglk2_band<true><<<cdiv(count, 256), 256, 0, st>>>(L, x, b, y, nR, nC, count);
+    else
+        k_redglk2_band<false><<<cdiv(count, 256), 256, 0, st>>>(L, x, b, y, nR, nC, count);
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
+// Krylov kernels.  Vectors of length n; a basis V holds m vectors at stride
+// ld.  Each block of 256 threads owns a contiguous chunk of KR_S*256 entries.
+// ------------------------------------------------------------------------
+constexpr int KR_S = 8;
+constexpr int KR_CHUNK = KR_S * 256;
+
+int krylov_blocks(size_t n) { return (int)((n + KR_CHUNK - 1) / KR_CHUNK); }
+
+__device__ __forceinline__ cd wave_sum(cd v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_mdot(const cd *__restrict__ V, size_t ld, int m,
+                                              const cd *__restrict__ w, size_t n,
+                                              cd *__restrict__ part, int with_norm)
+{
+    __shared__ cd red[4][PSTRIDE];
+    const size_t base = (size_t)blockIdx.x * KR_CHUNK + threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    cd wv[KR_S];
+#pragma unroll
+    for (int s = 0; s < KR_S; s++) {
+        const size_t p = base + (size_t)s * 256;
+        wv[s] = p < n ? w[p] : czero();
+    }
+    for (int i = 0; i < m; i++) {
+        const cd *vi = V + (size_t)i * ld;
+        cd acc = czero();
+#pragma unroll
+        for (int s = 0; s < KR_S; s++) {
+            const size_t p = base + (size_t)s * 256;
+            if (p < n) {
+                const cd v = vi[p];
+                acc.x = fma(v.x, wv[s].x, fma(v.y, wv[s].y, acc.x));
+                acc.y = fma(v.x, wv[s].y, fma(-v.y, wv[s].x, acc.y));
+            }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) red[wave][i] = acc;
+    }
+    if (with_norm) {
+        cd acc = czero();
+#pragma unroll
+        for (int s = 0; s < KR_S; s++) acc.x = fma(wv[s].x, wv[s].x, fma(wv[s].y, wv[s].y, acc.x));
+        acc = wave_sum(acc);
+        if (lane == 0) red[wave][m] = acc;
+    }
+    __syncthreads();
+    const int tot = m + (with_norm ? 1 : 0);
+    if ((int)threadIdx.x < tot) {
+        const int q = threadIdx.x;
+        part[(size_t)blockIdx.x * PSTRIDE + q] =
+            cadd(cadd(red[0][q], red[1][q]), cadd(red[2][q], red[3][q]));
+    }
+}
+
+hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd *part,
+                       int with_norm, hipStream_t st)
+{
+    k_mdot<<<krylov_blocks(n), 256, 0, st>>>(V, ld, m, w, n, part, with_norm);
+    HD_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *__restrict__ V,
+                                                 size_t ld, int m, const cd *__restrict__ c,
+                                                 size_t n, cd *__restrict__ part)
+{
+    __shared__ cd red[4];
+    const size_t base = (size_t)blockIdx.x * KR_CHUNK + threadIdx.x;
+    cd acc[KR_S];
+#pragma unroll
+    for (int s = 0; s < KR_S; s++) acc[s] = czero();
+    for (int i = 0; i < m; i++) {
+        const cd ci = c[i];
+        const cd *vi = V + (size_t)i * ld;
+#pragma unroll
+        for (int s = 0; s < KR_S; s++) {
+            const size_t p = base + (size_t)s * 256;
+            if (p < n) {
+                const cd v = vi[p];
+                acc[s].x = fma(ci.x, v.x, fma(-ci.y, v.y, acc[s].x));
+                acc[s].y = fma(ci.x, v.y, fma(ci.y, v.x, acc[s].y));
+            }
+        }
+    }
+    cd nrm = czero();
+#pragma unroll
+    for (int s = 0; s < KR_S; s++) {
+        const size_t p = base + (size_t)s * 256;
+        if (p < n) {
+            const cd o = csub(w[p], acc[s]);
+            w[p] = o;
+            nrm.x = fma(o.x, o.x, fma(o.y, o.y, nrm.x));
+        }
+    }
+    if (part) {
+        nrm = wave_sum(nrm);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            part[(size_t)blockIdx.x * PSTRIDE] = cadd(cadd(red[0], red[1]), cadd(red[2], red[3]));
+    }
+}
+
+hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *part,
+                          hipStream_t st)
+{
+    k_mupdate<<<krylov_blocks(n), 256, 0, st>>>(w, V, ld, m, c, n, part);
+    HD_LAUNCH_CHECK();
+}
+
+// out[i] = sum over blocks of part[blk][i] (fixed tree order); mode 0 store,
+// 1 accumulate, 2 store sqrt(real part) into out[0].
+__global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int nblk,
+                                                cd *__restrict__ out, int mode)
+{
+    __shared__ cd red[256];
+    const int i = blockIdx.x;
+    cd s = czero();
+    for (int b = threadIdx.x; b < nblk; b += 256) s = cadd(s, part[(size_t)b * PSTRIDE + i]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const cd v = red[0];
+        if (mode == 0)
+            out[i] = v;
+        else if (mode == 1)
+            out[i] = cadd(out[i], v);
+        else
+            out[i] = make_double2(sqrt(v.x), 0.0);
+    }
+}
+
+hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, hipStream_t st)
+{
+    k_reduce<<<m, 256, 0, st>>>(part, nblk, out, mode);
+    HD_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_scale(const cd *__restrict__ w, const cd *__restrict__ nrm,
+                                               cd *__restrict__ v, size_t n)
+{
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const double h = nrm[0].x;
+    v[p] = h > 0.0 ? cscal(1.0 / h, w[p]) : czero();
+}
+
+hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t st)
+{
+    k_scale<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(w, nrm, v, n);
+    HD_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_lincomb(const cd *__restrict__ V, size_t ld, int m,
+                                                 const cd *__restrict__ y, cd *__restrict__ out,
+                                                 size_t n, int accumulate)
+{
+    const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    cd s = accumulate ? out[p] : czero();
+    for (int i = 0; i < m; i++) s = cadd(s, cmul(y[i], V[(size_t)i * ld + p]));
+    out[p] = s;
+}
+
+hipError_t launch_lincomb(const cd *V, size_t ld, int m, const cd *y, cd *out, size_t n,
+                          int accumulate, hipStream_t st)
+{
+    k_lincomb<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(V, ld, m, y, out, n, accumulate);
+    HD_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_zero(cd *__restrict__ p, size_t n)
+{
+    const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < n) p[q] = czero();
+}
+
+hipError_t launch_zero(cd *p, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    k_zero<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, n);
+    HD_LAUNCH_CHECK();
+}
+
+// in and out may be the same buffer (each thread touches one entry)
+__global__ __launch_bounds__(256) void k_mask_copy(Lev L, const cd *in, cd *out)
+{
+    const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (size_t)L.nx * L.ny) return;
+    const int i = (int)(q % L.nx), j = (int)(q / L.nx);
+    out[q] = unknown(L, i, j) ? in[q] : czero();
+}
+
+hipError_t launch_mask_copy(const Lev &L, const cd *in, cd *out, hipStream_t st)
+{
+    const size_t n = (size_t)L.nx * L.ny;
+    k_mask_copy<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(L, in, out);
+    HD_LAUNCH_CHECK();
+}
+
+}  // namespace hd
