@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark: Helmholtz solves/s to a 1e-6 relative residual on one MI355X.
+
+One step = one complete solve of the large plain-method workload: the unit
+square, 4097 x 4097 nodes, constant k = 800, first-order Sommerfeld boundary,
+Gaussian source (sigma = 2h) at the centre, complex128, APD preconditioner
+(Bezier deflation vectors, ReD-Glk2 coarse operator, coarse GMRES(30) to 0.1,
+one CSLP V-cycle), FGMRES(50) to 1e-6.  Inputs are resident on the GPU before
+the timed region.
+
+Prints ONE JSON line with the contract fields plus:
+  roofline      the dominant kernel's algorithmic HBM bytes / its average
+                launch time (HIP events on the solver's stream, inside the
+                timed region), against the 8 TB/s HBM peak;
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
+                (rank 0 only), extrapolated to solves/s with the GPU run's
+                iteration counts.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Helmholtz solves/s to 1e-6 rel. residual; stencil+V-cycle HBM GB/s vs peak"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--roofline-kernel", default="mdot",
+                    help="kernel class whose roofline is reported")
+    ap.add_argument("--roofline-level", type=int, default=1,
+                    help="multigrid level of the timed kernel (-1 = any)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def kernels_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "hd_common.h"):
+        with open(os.path.join(ROOT, "paper_2308_06152_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
+    absent or taken on a different version of the kernels."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(f"{kernel}@{workload}")
+    if not e or e.get("kernels_sha") != kernels_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(w, info):
+    """Time the oracle on a bounded sample of the workload and extrapolate.
+
+    Sample (single-threaded C oracle, full 4097^2 grid): one A_h apply, one
+    coarse GMRES solve with 1 and with 3 fixed iterations (their difference
+    gives the cost of one inner iteration), and one A-DEF1 application with a
+    1-iteration coarse solve (the fine-grid part of an outer iteration).
+    Estimate of one solve = outer * (fine part + coarse-solve overhead + A_h)
+    + inner_total * (one inner iteration), with the GPU run's counts; the
+    outer Gram-Schmidt on the fine grid is left out (it favours the CPU)."""
+    import oracle
+    from paper_2308_06152_amd import inputs
+    oracle.build(force=False)
+    P = oracle.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+                       coarse_mode=oracle.CMODE_FIXED, coarse_iters=1,
+                       coarse_restart=w.coarse_restart)
+    nxc, nyc = oracle.coarse_dims(P)
+    v = inputs.random_complex((w.ny, w.nx), 11)
+    v1 = inputs.random_complex((nyc, nxc), 12)
+    t0 = time.perf_counter()
+    oracle.helm_apply(P, v)
+    t_a = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.coarse_solve(P, v1)
+    t_c1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.coarse_solve(P.replace(coarse_iters=3), v1)
+    t_c3 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.deflate_apply(P, v, oracle.DEFL_ADEF1)
+    t_d1 = time.perf_counter() - t0
+    per_inner = max((t_c3 - t_c1) / 2.0, 0.0)
+    overhead = max(t_c1 - per_inner, 0.0)
+    fine = max(t_d1 - t_c1, 0.0)
+    est = info["outer_iters"] * (fine + overhead + t_a) + info["inner_iters_total"] * per_inner
+    sample_s = t_a + t_c1 + t_c3 + t_d1
+    return {
+        "value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "sample": (f"single-threaded C oracle on the full {w.nx}x{w.ny} grid: A_h apply "
+                   f"{t_a:.2f}s, coarse GMRES 1 it {t_c1:.2f}s / 3 it {t_c3:.2f}s, A-DEF1 with "
+                   f"1 inner it {t_d1:.2f}s (sample {sample_s:.1f}s); extrapolated to "
+                   f"{info['outer_iters']} outer + {info['inner_iters_total']} inner iterations "
+                   f"= {est:.0f}s per solve"),
+        "est_seconds_per_solve": est,
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {a.gpus}); "
+              "the solve is not sharded across GPUs", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2308_06152_amd import helmdefl as H
+    from paper_2308_06152_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = inputs.large_plain() if a.workload == "large" else inputs.small_plain()
+    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+                 coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol, coarse_iters=w.coarse_maxit,
+                 coarse_restart=w.coarse_restart, restart=w.restart, tol=w.tol)
+    b = torch.from_numpy(w.rhs()).cuda()
+    x = torch.zeros_like(b)
+    torch.cuda.synchronize()
+    for _ in range(a.warmup):
+        S.solve(b, x)
+    kclass = H.KERNEL_CLASS_NAMES.index(a.roofline_kernel)
+    S.timing_enable(kclass, a.roofline_level)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(a.steps):
+        _, info = S.solve(b, x)
+        infos.append(info[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_launch, k_ms, k_bytes = S.timing_read()
+    S.timing_enable(-1, -1)
+    elapsed = t1 - t0
+    last = infos[-1]
+    if not all(i["converged"] for i in infos):
+        print("bench.py: a solve did not converge", file=sys.stderr)
+        sys.exit(1)
+    achieved = (k_bytes / 1e9) / (k_ms / 1e3) if k_ms > 0 else 0.0
+    traffic = measured_traffic(a.roofline_kernel, w.name)
+    line = {
+        "metric": METRIC,
+        "value": a.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name, "grid": f"{w.nx}x{w.ny}", "k": w.kconst,
+            "bc": "sommerfeld" if w.bc == H.BC_SOMMERFELD else "dirichlet",
+            "source": "gaussian sigma=2h" if w.source == "gauss" else "point",
+            "preconditioner": "APD (Bezier Z, " + ("ReD-Glk2" if w.coarse_op else "Galerkin")
+                              + " A_2h) + 1 CSLP V-cycle (1,0.5)",
+            "krylov": f"FGMRES({w.restart}) to {w.tol:g}",
+            "coarse_solve": f"GMRES({w.coarse_restart}) to {w.coarse_tol:g}",
+            "outer_iters": last["outer_iters"], "inner_iters_total": last["inner_iters_total"],
+            "relres": last["relres"],
+        },
+        "roofline": {
+            "kernel": a.roofline_kernel, "level": a.roofline_level, "bound": "hbm",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "launches": n_launch, "avg_launch_us": 1e3 * k_ms / max(n_launch, 1),
+            "alg_bytes_per_launch": k_bytes / max(n_launch, 1),
+        },
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, last)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
