@@ -126,14 +126,18 @@ hipError_t launch_redglk2(const Lev &Lc, const cd *x, const cd *b, cd *y, hipStr
 // ---- Krylov kernels ----
 // Number of partial-sum blocks used for vectors of length n.
 int krylov_blocks(size_t n);
-// part[blk][i] = sum conj(V_i) w over the block, i < m; slot m = |w|^2 if with_norm.
+// part[blk][i] = sum conj(V_i) w over the block, i < m; slot m = |w|^2 if
+// with_norm.  cond != nullptr: second Gram-Schmidt pass, a no-op unless the
+// reorthogonalisation test on cond (projections, then ||w||^2 at [jcond]) fires.
 hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd *part,
-                       int with_norm, hipStream_t st);
-// w -= sum_i c_i V_i; part[blk][0] = |w_new|^2 partial if part != nullptr.
-hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *part,
-                          hipStream_t st);
+                       int with_norm, const cd *cond, int jcond, hipStream_t st);
+// w -= sum_i c_i V_i; partn[blk] = |w_new|^2 partial if partn != nullptr.
+hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *partn,
+                          const cd *cond, int jcond, hipStream_t st);
 // out[i] (=|+=) sum_blk part[blk][i], i < m; mode 2: out[0] = (sqrt(sum re), 0).
-hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, hipStream_t st);
+// cond: as above; writes zeros when the second pass is skipped.
+hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, const cd *cond,
+                         int jcond, hipStream_t st);
 // v = w / nrm[0].x (v = 0 if the norm is 0).
 hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t st);
 // out (+)= sum_i y_i V_i.

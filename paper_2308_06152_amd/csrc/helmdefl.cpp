@@ -122,8 +122,9 @@ struct helm_ctx {
     int mc = 0;
     cd *Vc = nullptr, *wc = nullptr, *zc_ = nullptr, *xin = nullptr;
     // reductions
-    cd *part = nullptr;
+    cd *part = nullptr, *partn = nullptr;
     int part_blocks = 0;
+    long long n_arnoldi = 0, n_reorth = 0;
     cd *hbuf = nullptr, *ydev = nullptr;
     cd *hpin = nullptr;
     // outer FGMRES (allocated on first solve)
@@ -226,8 +227,8 @@ bool coarsenable(int nx, int ny) { return nx >= 5 && ny >= 5 && (nx & 1) && (ny 
 int vnorm(helm_ctx *h, const cd *v, size_t n, double *out)
 {
     const int nb = krylov_blocks(n);
-    HCHK(launch_mdot(nullptr, 0, 0, v, n, h->part, 1, h->st));
-    HCHK(launch_reduce(h->part, nb, 1, h->hbuf + 2 * PSTRIDE, 2, h->st));
+    HCHK(launch_mdot(nullptr, 0, 0, v, n, h->part, 1, nullptr, 0, h->st));
+    HCHK(launch_reduce(h->part, nb, 1, h->hbuf + 2 * PSTRIDE, 2, nullptr, 0, h->st));
     HCHK(hipMemcpyAsync(h->hpin + 2 * PSTRIDE, h->hbuf + 2 * PSTRIDE, sizeof(cd),
                         hipMemcpyDeviceToHost, h->st));
     HCHK(hipStreamSynchronize(h->st));
@@ -235,33 +236,42 @@ int vnorm(helm_ctx *h, const cd *v, size_t n, double *out)
     return HELM_OK;
 }
 
-// Arnoldi step by classical Gram-Schmidt with one reorthogonalisation (CGS2):
-// w is orthogonalised against V[0..j1-1], V[j1] = w / ||w||; col[0..j1-1]
-// receives the projections, *hn the norm.  One device->host copy, then sync.
-int arnoldi_cgs2(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col, double *hn,
+// Arnoldi step by classical Gram-Schmidt with conditional reorthogonalisation:
+// w is projected against V[0..j1-1] in one pass; a second pass runs only when
+// the device-side test of the DGKS kind finds cancellation (||w'|| below
+// ||w||/sqrt(2)); the kernels of the second pass read the first pass's
+// projections and decide by themselves, so the host never waits in between.
+// Then V[j1] = w / ||w||; col[0..j1-1] receives the projections (both passes
+// summed), *hn the norm.  One device->host copy, then sync.
+int arnoldi_step(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col, double *hn,
                  int lev)
 {
     const int nb = krylov_blocks(n);
     cd *h1 = h->hbuf, *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
-    for (int pass = 0; pass < 2; pass++) {
-        cd *hc = pass == 0 ? h1 : h2;
-        {
-            Timed tm(h, HELM_K_DOT, lev, 16.0 * (j1 + 1) * n);
-            HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h->st));
-        }
-        HCHK(launch_reduce(h->part, nb, j1, hc, 0, h->st));
-        {
-            Timed tm(h, HELM_K_UPDATE, lev, 16.0 * (j1 + 2) * n);
-            HCHK(launch_mupdate(w, V, ld, j1, hc, n, pass == 1 ? h->part : nullptr, h->st));
-        }
+    {
+        Timed tm(h, HELM_K_DOT, lev, 16.0 * (j1 + 1) * n);
+        HCHK(launch_mdot(V, ld, j1, w, n, h->part, 1, nullptr, 0, h->st));
     }
-    HCHK(launch_reduce(h->part, nb, 1, nr, 2, h->st));
+    HCHK(launch_reduce(h->part, nb, j1 + 1, h1, 0, nullptr, 0, h->st));  // h1[j1] = ||w||^2
+    {
+        Timed tm(h, HELM_K_UPDATE, lev, 16.0 * (j1 + 2) * n);
+        HCHK(launch_mupdate(w, V, ld, j1, h1, n, h->partn, nullptr, 0, h->st));
+    }
+    HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
+    HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->st));
+    HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, h->st));
+    HCHK(launch_reduce(h->partn, nb, 1, nr, 2, nullptr, 0, h->st));
     HCHK(launch_scale(w, nr, V + (size_t)j1 * ld, n, h->st));
     HCHK(hipMemcpyAsync(h->hpin, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd), hipMemcpyDeviceToHost,
                         h->st));
     HCHK(hipStreamSynchronize(h->st));
-    for (int i = 0; i < j1; i++)
+    bool reorth = false;
+    for (int i = 0; i < j1; i++) {
         col[i] = zc(h->hpin[i].x + h->hpin[PSTRIDE + i].x, h->hpin[i].y + h->hpin[PSTRIDE + i].y);
+        reorth |= h->hpin[PSTRIDE + i].x != 0.0 || h->hpin[PSTRIDE + i].y != 0.0;
+    }
+    h->n_arnoldi++;
+    h->n_reorth += reorth;
     *hn = h->hpin[2 * PSTRIDE].x;
     return HELM_OK;
 }
@@ -380,7 +390,7 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
             RCHK(vcycle(h, 1, vj, h->zc_, 0, nullptr));
             RCHK(coarse_apply(h, h->zc_, nullptr, h->wc));
             double hn;
-            RCHK(arnoldi_cgs2(h, h->Vc, nc, j + 1, h->wc, nc, col.data(), &hn, 1));
+            RCHK(arnoldi_step(h, h->Vc, nc, j + 1, h->wc, nc, col.data(), &hn, 1));
             const double res = gv.add_column(j, col.data(), hn);
             it++;
             jend = j + 1;
@@ -494,7 +504,7 @@ int solve_one(helm_ctx *h, const cd *b, cd *x, helm_solve_info *info)
                 if (inner > inf.inner_iters_max) inf.inner_iters_max = inner;
                 RCHK(apply_A(h, 0, zj, nullptr, h->w));
                 double hn;
-                RCHK(arnoldi_cgs2(h, h->V, n, j + 1, h->w, n, col.data(), &hn, 0));
+                RCHK(arnoldi_step(h, h->V, n, j + 1, h->w, n, col.data(), &hn, 0));
                 const double res = gv.add_column(j, col.data(), hn);
                 inf.outer_iters++;
                 jend = j + 1;
@@ -617,6 +627,7 @@ void release(helm_ctx *h)
     dfree(h->zc_);
     dfree(h->xin);
     dfree(h->part);
+    dfree(h->partn);
     dfree(h->hbuf);
     dfree(h->ydev);
     dfree(h->V);
@@ -731,6 +742,7 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (!rc) rc = dalloc(&h->xin, nc);
     h->part_blocks = krylov_blocks(nf);
     if (!rc) rc = dalloc(&h->part, (size_t)h->part_blocks * PSTRIDE);
+    if (!rc) rc = dalloc(&h->partn, (size_t)h->part_blocks * PSTRIDE);
     if (!rc) rc = dalloc(&h->hbuf, (size_t)HBUF);
     if (!rc) rc = dalloc(&h->ydev, (size_t)PSTRIDE);
     if (!rc && hipHostMalloc((void **)&h->hpin, HBUF * sizeof(cd)) != hipSuccess) {

@@ -680,12 +680,55 @@ hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, hipStre
 
 // ------------------------------------------------------------------------
 // Krylov kernels.  Vectors of length n; a basis V holds m vectors at stride
-// ld.  Each block of 256 threads owns a contiguous chunk of KR_S*256 entries.
+// ld.  The grid is sized to the number of blocks the chip holds at once
+// (times a whole number of rounds), and each block owns one contiguous chunk
+// of the vector, so every block does the same work and no tail round is left.
+// Each thread keeps up to KR_S entries of w (or of its update) in registers.
 // ------------------------------------------------------------------------
-constexpr int KR_S = 8;
-constexpr int KR_CHUNK = KR_S * 256;
+constexpr int KR_S = 16;
 
-int krylov_blocks(size_t n) { return (int)((n + KR_CHUNK - 1) / KR_CHUNK); }
+static int g_resident = 0;  // Krylov blocks resident on the device at once
+
+__global__ void k_mdot(const cd *__restrict__ V, size_t ld, int m, const cd *__restrict__ w,
+                       size_t n, size_t chunk, cd *__restrict__ part, int with_norm,
+                       const cd *__restrict__ cond, int jcond);
+__global__ void k_mupdate(cd *__restrict__ w, const cd *__restrict__ V, size_t ld, int m,
+                          const cd *__restrict__ c, size_t n, size_t chunk,
+                          cd *__restrict__ partn, const cd *__restrict__ cond, int jcond);
+
+static int resident_blocks()
+{
+    if (g_resident > 0) return g_resident;
+    int dev = 0, ncu = 0, b1 = 0, b2 = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        ncu = 256;
+    (void)hipGetLastError();
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, (const void *)k_mdot, 256, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, (const void *)k_mupdate, 256, 0) !=
+            hipSuccess)
+        b1 = b2 = 4;
+    (void)hipGetLastError();
+    int b = b1 < b2 ? b1 : b2;
+    if (b < 1) b = 1;
+    g_resident = ncu * b;
+    return g_resident;
+}
+
+int krylov_blocks(size_t n)
+{
+    const size_t res = (size_t)resident_blocks();
+    const size_t per_round = res * 256 * KR_S;
+    const size_t rounds = (n + per_round - 1) / per_round;
+    size_t nb = res * (rounds > 0 ? rounds : 1);
+    // never more blocks than 256-entry slices of the vector
+    const size_t maxb = (n + 255) / 256;
+    if (nb > maxb) nb = maxb > 0 ? maxb : 1;
+    return (int)nb;
+}
+
+static size_t krylov_chunk(size_t n, int nb) { return (n + nb - 1) / nb; }
 
 __device__ __forceinline__ cd wave_sum(cd v)
 {
@@ -697,33 +740,75 @@ __device__ __forceinline__ cd wave_sum(cd v)
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_mdot(const cd *__restrict__ V, size_t ld, int m,
-                                              const cd *__restrict__ w, size_t n,
-                                              cd *__restrict__ part, int with_norm)
+// Reorthogonalisation test of the DGKS kind on the first Gram-Schmidt pass:
+// hb[0..j1) are the projections h_i, hb[j1].x = ||w||^2 before projection.
+// With ||w'||^2 = ||w||^2 - sum |h_i|^2, a second pass is needed when
+// ||w'|| < ||w|| / sqrt(2).  Every kernel of the second pass evaluates this
+// same expression in the same order, so they agree.
+__device__ __forceinline__ bool need_reorth(const cd *__restrict__ hb, int j1)
 {
+    double s = 0.0;
+    for (int i = 0; i < j1; i++) s = fma(hb[i].x, hb[i].x, fma(hb[i].y, hb[i].y, s));
+    const double w2 = hb[j1].x;
+    return !(w2 - s > 0.5 * w2);
+}
+
+// part[blk][i] = sum over the block's chunk of conj(V_i) w, i < m; slot m gets
+// |w|^2 when with_norm.  If cond != nullptr the kernel is the second
+// Gram-Schmidt pass and exits at once unless need_reorth(cond, jcond).
+__global__ __launch_bounds__(256) void k_mdot(const cd *__restrict__ V, size_t ld, int m,
+                                              const cd *__restrict__ w, size_t n, size_t chunk,
+                                              cd *__restrict__ part, int with_norm,
+                                              const cd *__restrict__ cond, int jcond)
+{
+    if (cond && !need_reorth(cond, jcond)) return;
     __shared__ cd red[4][PSTRIDE];
-    const size_t base = (size_t)blockIdx.x * KR_CHUNK + threadIdx.x;
+    const size_t base = (size_t)blockIdx.x * chunk;
+    size_t end = base + chunk;
+    if (end > n) end = n;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     cd wv[KR_S];
 #pragma unroll
     for (int s = 0; s < KR_S; s++) {
-        const size_t p = base + (size_t)s * 256;
-        wv[s] = p < n ? w[p] : czero();
+        const size_t p = base + threadIdx.x + (size_t)s * 256;
+        wv[s] = p < end ? w[p] : czero();
     }
-    for (int i = 0; i < m; i++) {
-        const cd *vi = V + (size_t)i * ld;
-        cd acc = czero();
+    int i = 0;
+    for (; i + 1 < m; i += 2) {
+        const cd *v0 = V + (size_t)i * ld, *v1 = V + (size_t)(i + 1) * ld;
+        cd a0 = czero(), a1 = czero();
 #pragma unroll
         for (int s = 0; s < KR_S; s++) {
-            const size_t p = base + (size_t)s * 256;
-            if (p < n) {
-                const cd v = vi[p];
-                acc.x = fma(v.x, wv[s].x, fma(v.y, wv[s].y, acc.x));
-                acc.y = fma(v.x, wv[s].y, fma(-v.y, wv[s].x, acc.y));
+            const size_t p = base + threadIdx.x + (size_t)s * 256;
+            if (p < end) {
+                const cd x0 = v0[p], x1 = v1[p];
+                a0.x = fma(x0.x, wv[s].x, fma(x0.y, wv[s].y, a0.x));
+                a0.y = fma(x0.x, wv[s].y, fma(-x0.y, wv[s].x, a0.y));
+                a1.x = fma(x1.x, wv[s].x, fma(x1.y, wv[s].y, a1.x));
+                a1.y = fma(x1.x, wv[s].y, fma(-x1.y, wv[s].x, a1.y));
             }
         }
-        acc = wave_sum(acc);
-        if (lane == 0) red[wave][i] = acc;
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        if (lane == 0) {
+            red[wave][i] = a0;
+            red[wave][i + 1] = a1;
+        }
+    }
+    if (i < m) {
+        const cd *v0 = V + (size_t)i * ld;
+        cd a0 = czero();
+#pragma unroll
+        for (int s = 0; s < KR_S; s++) {
+            const size_t p = base + threadIdx.x + (size_t)s * 256;
+            if (p < end) {
+                const cd x0 = v0[p];
+                a0.x = fma(x0.x, wv[s].x, fma(x0.y, wv[s].y, a0.x));
+                a0.y = fma(x0.x, wv[s].y, fma(-x0.y, wv[s].x, a0.y));
+            }
+        }
+        a0 = wave_sum(a0);
+        if (lane == 0) red[wave][i] = a0;
     }
     if (with_norm) {
         cd acc = czero();
@@ -742,67 +827,97 @@ __global__ __launch_bounds__(256) void k_mdot(const cd *__restrict__ V, size_t l
 }
 
 hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd *part,
-                       int with_norm, hipStream_t st)
+                       int with_norm, const cd *cond, int jcond, hipStream_t st)
 {
-    k_mdot<<<krylov_blocks(n), 256, 0, st>>>(V, ld, m, w, n, part, with_norm);
+    const int nb = krylov_blocks(n);
+    k_mdot<<<nb, 256, 0, st>>>(V, ld, m, w, n, krylov_chunk(n, nb), part, with_norm, cond, jcond);
     HD_LAUNCH_CHECK();
 }
 
+// w -= sum_i c_i V_i over the block's chunk; partn[blk] = |w_new|^2 partial
+// (if partn).  cond: second pass, skipped unless need_reorth(cond, jcond).
 __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *__restrict__ V,
                                                  size_t ld, int m, const cd *__restrict__ c,
-                                                 size_t n, cd *__restrict__ part)
+                                                 size_t n, size_t chunk, cd *__restrict__ partn,
+                                                 const cd *__restrict__ cond, int jcond)
 {
+    if (cond && !need_reorth(cond, jcond)) return;
     __shared__ cd red[4];
-    const size_t base = (size_t)blockIdx.x * KR_CHUNK + threadIdx.x;
+    const size_t base = (size_t)blockIdx.x * chunk;
+    size_t end = base + chunk;
+    if (end > n) end = n;
     cd acc[KR_S];
 #pragma unroll
     for (int s = 0; s < KR_S; s++) acc[s] = czero();
-    for (int i = 0; i < m; i++) {
-        const cd ci = c[i];
-        const cd *vi = V + (size_t)i * ld;
+    int i = 0;
+    for (; i + 1 < m; i += 2) {
+        const cd c0 = c[i], c1 = c[i + 1];
+        const cd *v0 = V + (size_t)i * ld, *v1 = V + (size_t)(i + 1) * ld;
 #pragma unroll
         for (int s = 0; s < KR_S; s++) {
-            const size_t p = base + (size_t)s * 256;
-            if (p < n) {
-                const cd v = vi[p];
-                acc[s].x = fma(ci.x, v.x, fma(-ci.y, v.y, acc[s].x));
-                acc[s].y = fma(ci.x, v.y, fma(ci.y, v.x, acc[s].y));
+            const size_t p = base + threadIdx.x + (size_t)s * 256;
+            if (p < end) {
+                const cd x0 = v0[p], x1 = v1[p];
+                acc[s].x = fma(c0.x, x0.x, fma(-c0.y, x0.y, acc[s].x));
+                acc[s].y = fma(c0.x, x0.y, fma(c0.y, x0.x, acc[s].y));
+                acc[s].x = fma(c1.x, x1.x, fma(-c1.y, x1.y, acc[s].x));
+                acc[s].y = fma(c1.x, x1.y, fma(c1.y, x1.x, acc[s].y));
+            }
+        }
+    }
+    if (i < m) {
+        const cd c0 = c[i];
+        const cd *v0 = V + (size_t)i * ld;
+#pragma unroll
+        for (int s = 0; s < KR_S; s++) {
+            const size_t p = base + threadIdx.x + (size_t)s * 256;
+            if (p < end) {
+                const cd x0 = v0[p];
+                acc[s].x = fma(c0.x, x0.x, fma(-c0.y, x0.y, acc[s].x));
+                acc[s].y = fma(c0.x, x0.y, fma(c0.y, x0.x, acc[s].y));
             }
         }
     }
     cd nrm = czero();
 #pragma unroll
     for (int s = 0; s < KR_S; s++) {
-        const size_t p = base + (size_t)s * 256;
-        if (p < n) {
+        const size_t p = base + threadIdx.x + (size_t)s * 256;
+        if (p < end) {
             const cd o = csub(w[p], acc[s]);
             w[p] = o;
             nrm.x = fma(o.x, o.x, fma(o.y, o.y, nrm.x));
         }
     }
-    if (part) {
+    if (partn) {
         nrm = wave_sum(nrm);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
         __syncthreads();
         if (threadIdx.x == 0)
-            part[(size_t)blockIdx.x * PSTRIDE] = cadd(cadd(red[0], red[1]), cadd(red[2], red[3]));
+            partn[(size_t)blockIdx.x * PSTRIDE] = cadd(cadd(red[0], red[1]), cadd(red[2], red[3]));
     }
 }
 
-hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *part,
-                          hipStream_t st)
+hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *partn,
+                          const cd *cond, int jcond, hipStream_t st)
 {
-    k_mupdate<<<krylov_blocks(n), 256, 0, st>>>(w, V, ld, m, c, n, part);
+    const int nb = krylov_blocks(n);
+    k_mupdate<<<nb, 256, 0, st>>>(w, V, ld, m, c, n, krylov_chunk(n, nb), partn, cond, jcond);
     HD_LAUNCH_CHECK();
 }
 
 // out[i] = sum over blocks of part[blk][i] (fixed tree order); mode 0 store,
-// 1 accumulate, 2 store sqrt(real part) into out[0].
+// 1 accumulate, 2 store sqrt(real part).  cond: second-pass reduction, which
+// stores zeros unless need_reorth(cond, jcond).
 __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int nblk,
-                                                cd *__restrict__ out, int mode)
+                                                cd *__restrict__ out, int mode,
+                                                const cd *__restrict__ cond, int jcond)
 {
     __shared__ cd red[256];
     const int i = blockIdx.x;
+    if (cond && !need_reorth(cond, jcond)) {
+        if (threadIdx.x == 0) out[i] = czero();
+        return;
+    }
     cd s = czero();
     for (int b = threadIdx.x; b < nblk; b += 256) s = cadd(s, part[(size_t)b * PSTRIDE + i]);
     red[threadIdx.x] = s;
@@ -822,9 +937,10 @@ __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int
     }
 }
 
-hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, hipStream_t st)
+hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, const cd *cond,
+                         int jcond, hipStream_t st)
 {
-    k_reduce<<<m, 256, 0, st>>>(part, nblk, out, mode);
+    k_reduce<<<m, 256, 0, st>>>(part, nblk, out, mode, cond, jcond);
     HD_LAUNCH_CHECK();
 }
 
