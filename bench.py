@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--roofline-level", type=int, default=1,
                     help="multigrid level of the timed kernel (-1 = any)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (out = in * 1) three times, "
+                         "the reference for scaling rocprofv3 byte counters")
     return ap.parse_args()
 
 
@@ -67,7 +70,7 @@ def measured_traffic(kernel, workload):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(w, info):
+def cpu_baseline(w, info, coarsest_nodes):
     """Time the oracle on a bounded sample of the workload and extrapolate.
 
     Sample (single-threaded C oracle, full 4097^2 grid): one A_h apply, one
@@ -82,7 +85,7 @@ def cpu_baseline(w, info):
     oracle.build(force=False)
     P = oracle.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
                        coarse_mode=oracle.CMODE_FIXED, coarse_iters=1,
-                       coarse_restart=w.coarse_restart)
+                       coarse_restart=w.coarse_restart, coarsest_nodes=coarsest_nodes)
     nxc, nyc = oracle.coarse_dims(P)
     v = inputs.random_complex((w.ny, w.nx), 11)
     v1 = inputs.random_complex((nyc, nxc), 12)
@@ -129,6 +132,13 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.calibrate_copy:
+        src = torch.ones(1 << 26, dtype=torch.complex128, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.large_plain() if a.workload == "large" else inputs.small_plain()
     S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
                  coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol, coarse_iters=w.coarse_maxit,
@@ -190,7 +200,7 @@ def main():
         },
     }
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, last)
+        line["cpu_baseline"] = cpu_baseline(w, last, S.opts.coarsest_nodes)
     print(json.dumps(line), flush=True)
 
 

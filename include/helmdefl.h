@@ -78,6 +78,11 @@ typedef struct {
     double tol;              /* outer relative residual target (default 1e-6)   */
     int x0_given;            /* helm_solve: 1 = x holds the initial guess       */
     int force_iters;         /* >0: run exactly this many outer iterations      */
+    int coarsest_nodes;      /* predefined coarsest multigrid grid (Section 4):
+                                below level 1, stop coarsening once a level has
+                                <= this many nodes; that level is solved exactly
+                                (default 1089 = 33 x 33; 0 = down to 3 x 3;
+                                at most 2048) */
 } helm_opts;
 
 /* Per right-hand side result of helm_solve. */
@@ -98,8 +103,9 @@ int helm_opts_default(helm_opts *o);
 /* Create a solver handle.
  *  g        grid; nx, ny >= 5 and odd (the deflation coarse grid is
  *           ((nx+1)/2) x ((ny+1)/2), Section 4), else HELM_EGRID.  Multigrid
- *           levels coarsen while both counts are odd and >= 5; the coarsest
- *           level (at most 2048 nodes) is solved exactly.
+ *           levels coarsen while both counts are odd and >= 5 and (below level
+ *           1) the level has more than opts.coarsest_nodes nodes; the coarsest
+ *           level (at most 2048 nodes, else HELM_EGRID) is solved exactly.
  *  k_dev    device pointer to the real FP64 wavenumber field [ny][nx]
  *           (k = 2 pi f / c, Section 2), or NULL to use k_const everywhere.
  *           Copied at create; not retained.

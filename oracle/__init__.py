@@ -50,6 +50,7 @@ class _Problem(ctypes.Structure):
         ("coarse_mode", ctypes.c_int), ("coarse_iters", ctypes.c_int),
         ("coarse_restart", ctypes.c_int), ("coarse_tol", ctypes.c_double),
         ("precond", ctypes.c_int),
+        ("coarsest_nodes", ctypes.c_int),
     ]
 
 
@@ -81,6 +82,7 @@ class Problem:
     coarse_restart: int = 30
     coarse_tol: float = 1e-1
     precond: int = PRECOND_VCYCLE
+    coarsest_nodes: int = 0           # predefined coarsest grid (0 = down to 3x3)
 
     def replace(self, **kw) -> "Problem":
         return dataclasses.replace(self, **kw)
@@ -100,6 +102,7 @@ class Problem:
         p.coarse_mode, p.coarse_iters = self.coarse_mode, self.coarse_iters
         p.coarse_restart, p.coarse_tol = self.coarse_restart, self.coarse_tol
         p.precond = self.precond
+        p.coarsest_nodes = self.coarsest_nodes
         return p, keep
 
 
@@ -115,8 +118,9 @@ def lib() -> ctypes.CDLL:
         P = ctypes.POINTER(_Problem)
         D = ctypes.POINTER(ctypes.c_double)
         IP = ctypes.POINTER(ctypes.c_int)
-        L.ora_num_levels.argtypes = [ctypes.c_int, ctypes.c_int]
-        L.ora_level_dims.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, IP, IP]
+        L.ora_num_levels.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.ora_level_dims.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, IP,
+                                     IP]
         for name in ("ora_helm_apply", "ora_cslp_apply", "ora_z_prolong", "ora_z_restrict",
                      "ora_coarse_apply", "ora_direct_solve", "ora_coarse_direct_solve"):
             getattr(L, name).argtypes = [P, D, D]
@@ -151,18 +155,19 @@ def _check(rc: int, what: str):
         raise OracleError(f"{what} failed with code {rc}")
 
 
-def num_levels(nx: int, ny: int) -> int:
-    return lib().ora_num_levels(nx, ny)
+def num_levels(nx: int, ny: int, coarsest_nodes: int = 0) -> int:
+    return lib().ora_num_levels(nx, ny, coarsest_nodes)
 
 
-def level_dims(nx: int, ny: int, level: int) -> tuple[int, int]:
+def level_dims(nx: int, ny: int, level: int, coarsest_nodes: int = 0) -> tuple[int, int]:
     a, b = ctypes.c_int(), ctypes.c_int()
-    _check(lib().ora_level_dims(nx, ny, level, ctypes.byref(a), ctypes.byref(b)), "level_dims")
+    _check(lib().ora_level_dims(nx, ny, coarsest_nodes, level, ctypes.byref(a),
+                                ctypes.byref(b)), "level_dims")
     return a.value, b.value
 
 
 def coarse_dims(p: Problem) -> tuple[int, int]:
-    return level_dims(p.nx, p.ny, 1)
+    return level_dims(p.nx, p.ny, 1, p.coarsest_nodes)
 
 
 def _unary(name, p: Problem, x, in_shape, out_shape):
@@ -216,7 +221,7 @@ def coarse_direct_solve(p: Problem, b):
 
 def vcycle(p: Problem, r, level: int = 0):
     """z = one CSLP V-cycle applied to r, starting at `level`."""
-    nx, ny = level_dims(p.nx, p.ny, level)
+    nx, ny = level_dims(p.nx, p.ny, level, p.coarsest_nodes)
     c, keep = p._c()
     r = _cin(r, (ny, nx))
     z = np.empty((ny, nx), np.complex128)

@@ -56,13 +56,18 @@ typedef struct {
 
 /* A level is coarsened (standard coarsening, h -> 2h, coarse (I,J) sits on fine
  * (2I,2J); Section 4, parallel multigrid) while both point counts are odd and
- * at least 5. */
+ * at least 5.  Section 4 stops coarsening at a manually predefined coarsest
+ * grid and solves the problem there: levels beyond the first coarse one are
+ * only made while the current level has more than coarsest_nodes nodes
+ * (0 = coarsen as far as possible).  The deflation coarse grid (level 1) is
+ * always made. */
 static int coarsenable(int nx, int ny) { return nx >= 5 && ny >= 5 && (nx & 1) && (ny & 1); }
 
-int ora_num_levels(int nx, int ny)
+int ora_num_levels(int nx, int ny, int coarsest_nodes)
 {
     int n = 1;
-    while (coarsenable(nx, ny) && n < MAXLEV) {
+    while (coarsenable(nx, ny) && n < MAXLEV &&
+           (n == 1 || (long)nx * (long)ny > (long)coarsest_nodes)) {
         nx = (nx + 1) / 2;
         ny = (ny + 1) / 2;
         n++;
@@ -70,9 +75,9 @@ int ora_num_levels(int nx, int ny)
     return n;
 }
 
-int ora_level_dims(int nx, int ny, int l, int *lnx, int *lny)
+int ora_level_dims(int nx, int ny, int coarsest_nodes, int l, int *lnx, int *lny)
 {
-    if (l < 0 || l >= ora_num_levels(nx, ny)) return ORA_EINVAL;
+    if (l < 0 || l >= ora_num_levels(nx, ny, coarsest_nodes)) return ORA_EINVAL;
     for (int q = 0; q < l; q++) {
         nx = (nx + 1) / 2;
         ny = (ny + 1) / 2;
@@ -108,7 +113,8 @@ static int build_hier(const ora_problem *p, hier_t *H)
     memset(H, 0, sizeof(*H));
     if (!p || p->nx < 3 || p->ny < 3 || !(p->hx > 0) || !(p->hy > 0)) return ORA_EINVAL;
     if (p->bc != ORA_BC_DIRICHLET && p->bc != ORA_BC_SOMMERFELD) return ORA_EINVAL;
-    H->nlev = ora_num_levels(p->nx, p->ny);
+    if (p->coarsest_nodes < 0) return ORA_EINVAL;
+    H->nlev = ora_num_levels(p->nx, p->ny, p->coarsest_nodes);
     for (int l = 0; l < H->nlev; l++) {
         lvl_t *g = &H->L[l];
         if (l == 0) {

@@ -60,6 +60,9 @@ typedef struct {
     int coarse_restart;       /* restart length of the inner GMRES             */
     double coarse_tol;        /* TOL: relative residual target                 */
     int precond;              /* ORA_PRECOND_*: what stands for M^{-1}          */
+    int coarsest_nodes;       /* predefined coarsest grid: stop coarsening below
+                                 level 1 once a level has <= this many nodes
+                                 (0 = coarsen down to 3 x 3)                   */
 } ora_problem;
 
 typedef struct {
@@ -71,8 +74,8 @@ typedef struct {
 } ora_info;
 
 /* Level hierarchy of the V-cycle: number of levels and the dims of level l. */
-int ora_num_levels(int nx, int ny);
-int ora_level_dims(int nx, int ny, int l, int *lnx, int *lny);
+int ora_num_levels(int nx, int ny, int coarsest_nodes);
+int ora_level_dims(int nx, int ny, int coarsest_nodes, int l, int *lnx, int *lny);
 
 /* y = A_h x (5-point Helmholtz operator with the boundary closure). */
 int ora_helm_apply(const ora_problem *p, const double *x, double *y);

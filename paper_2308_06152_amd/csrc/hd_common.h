@@ -104,11 +104,14 @@ __host__ __device__ inline bool coef5(const Lev &L, cd s, int i, int j, cd &ap, 
 // y = (-Lap - s k^2) x, or y = b - (-Lap - s k^2) x when b != nullptr.
 hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hipStream_t st);
 // rc = FW( r - M (omega D^-1 r) ): pre-smooth from zero, residual, restriction.
-hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r, cd *rc,
-                          hipStream_t st);
-// out (+)= x2 + omega D^-1 (r - M x2), x2 = omega D^-1 r + P ec  [+ Z v2].
+// The right-hand side is rs[0].x * r when rs != nullptr (a lazily normalised
+// Krylov vector).
+hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
+                          const cd *rs, cd *rc, hipStream_t st);
+// out (+)= x2 + omega D^-1 (r - M x2), x2 = omega D^-1 r + P ec  [+ Z v2];
+// right-hand side scaled by rs[0].x as above.
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
-                        const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
+                        const cd *rs, const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
                         hipStream_t st);
 // x = Minv r on the coarsest level (dense inverse, n x n, row major).
 hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st);
@@ -131,13 +134,15 @@ int krylov_blocks(size_t n);
 // reorthogonalisation test on cond (projections, then ||w||^2 at [jcond]) fires.
 hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd *part,
                        int with_norm, const cd *cond, int jcond, hipStream_t st);
-// w -= sum_i c_i V_i; partn[blk] = |w_new|^2 partial if partn != nullptr.
+// w -= sum_i c_i sig_i V_i (sig_i = 1 if sig == nullptr); partn[blk] =
+// |w_new|^2 partial if partn != nullptr.
 hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *partn,
-                          const cd *cond, int jcond, hipStream_t st);
-// out[i] (=|+=) sum_blk part[blk][i], i < m; mode 2: out[0] = (sqrt(sum re), 0).
-// cond: as above; writes zeros when the second pass is skipped.
+                          const cd *cond, int jcond, const cd *sig, hipStream_t st);
+// out[i] (=|+=) sum_blk part[blk][i], i < m (mode 0: times sig[i] for
+// i < nsig); mode 2: out[0] = (sqrt(sum re), 0) and sig_out[0] = its
+// reciprocal.  cond: as above; writes zeros when the second pass is skipped.
 hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, const cd *cond,
-                         int jcond, hipStream_t st);
+                         int jcond, const cd *sig, int nsig, cd *sig_out, hipStream_t st);
 // v = w / nrm[0].x (v = 0 if the norm is 0).
 hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t st);
 // out (+)= sum_i y_i V_i.

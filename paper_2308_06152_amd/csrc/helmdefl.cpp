@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -126,7 +127,9 @@ struct helm_ctx {
     int part_blocks = 0;
     long long n_arnoldi = 0, n_reorth = 0;
     cd *hbuf = nullptr, *ydev = nullptr;
-    cd *hpin = nullptr;
+    cd *sig = nullptr;   // 1/||u_i|| of the lazily normalised inner basis
+    cd *hpin = nullptr;  // pinned: two Arnoldi read-back slots, y staging, norm
+    hipEvent_t ev_slot[2] = {nullptr, nullptr};
     // outer FGMRES (allocated on first solve)
     int m = 0;
     cd *V = nullptr, *Z = nullptr, *w = nullptr, *bm = nullptr;
@@ -223,16 +226,22 @@ void dfree(void *p)
 
 bool coarsenable(int nx, int ny) { return nx >= 5 && ny >= 5 && (nx & 1) && (ny & 1); }
 
-// ||v|| of a device vector (synchronises).
-int vnorm(helm_ctx *h, const cd *v, size_t n, double *out)
+// Pinned read-back layout: slot q of the Arnoldi scalars at q*HBUF, the
+// least-squares solution staging at 2*HBUF, the norm read-back at 3*HBUF.
+constexpr int PIN_Y = 2 * HBUF, PIN_NORM = 3 * HBUF, PIN_TOTAL = 4 * HBUF;
+
+// ||v|| of a device vector (synchronises); also stores 1/||v|| in sig_out[0]
+// when given.
+int vnorm(helm_ctx *h, const cd *v, size_t n, double *out, cd *sig_out = nullptr)
 {
     const int nb = krylov_blocks(n);
     HCHK(launch_mdot(nullptr, 0, 0, v, n, h->part, 1, nullptr, 0, h->st));
-    HCHK(launch_reduce(h->part, nb, 1, h->hbuf + 2 * PSTRIDE, 2, nullptr, 0, h->st));
-    HCHK(hipMemcpyAsync(h->hpin + 2 * PSTRIDE, h->hbuf + 2 * PSTRIDE, sizeof(cd),
+    HCHK(launch_reduce(h->part, nb, 1, h->hbuf + 2 * PSTRIDE, 2, nullptr, 0, nullptr, 0, sig_out,
+                       h->st));
+    HCHK(hipMemcpyAsync(h->hpin + PIN_NORM, h->hbuf + 2 * PSTRIDE, sizeof(cd),
                         hipMemcpyDeviceToHost, h->st));
     HCHK(hipStreamSynchronize(h->st));
-    *out = h->hpin[2 * PSTRIDE].x;
+    *out = h->hpin[PIN_NORM].x;
     return HELM_OK;
 }
 
@@ -252,15 +261,16 @@ int arnoldi_step(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col
         Timed tm(h, HELM_K_DOT, lev, 16.0 * (j1 + 1) * n);
         HCHK(launch_mdot(V, ld, j1, w, n, h->part, 1, nullptr, 0, h->st));
     }
-    HCHK(launch_reduce(h->part, nb, j1 + 1, h1, 0, nullptr, 0, h->st));  // h1[j1] = ||w||^2
+    HCHK(launch_reduce(h->part, nb, j1 + 1, h1, 0, nullptr, 0, nullptr, 0, nullptr,
+                       h->st));  // h1[j1] = ||w||^2
     {
         Timed tm(h, HELM_K_UPDATE, lev, 16.0 * (j1 + 2) * n);
-        HCHK(launch_mupdate(w, V, ld, j1, h1, n, h->partn, nullptr, 0, h->st));
+        HCHK(launch_mupdate(w, V, ld, j1, h1, n, h->partn, nullptr, 0, nullptr, h->st));
     }
     HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
-    HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->st));
-    HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, h->st));
-    HCHK(launch_reduce(h->partn, nb, 1, nr, 2, nullptr, 0, h->st));
+    HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, nullptr, 0, nullptr, h->st));
+    HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, nullptr, h->st));
+    HCHK(launch_reduce(h->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, nullptr, h->st));
     HCHK(launch_scale(w, nr, V + (size_t)j1 * ld, n, h->st));
     HCHK(hipMemcpyAsync(h->hpin, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd), hipMemcpyDeviceToHost,
                         h->st));
@@ -276,10 +286,57 @@ int arnoldi_step(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col
     return HELM_OK;
 }
 
+// Arnoldi step of the inner solve on a lazily normalised basis: V[i] holds
+// u_i with v_i = sig[i] u_i.  The new vector w = A z already sits in V[j1];
+// it is orthogonalised in place (same conditional second pass as above) and
+// sig[j1] = 1/||w'|| is stored, so no scaling pass is needed.  Everything is
+// enqueued; the scalars are copied to pinned slot `slot` and ev_slot[slot]
+// is recorded.  arnoldi_finish() waits for that event.
+int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int lev, int slot)
+{
+    const int nb = krylov_blocks(n);
+    cd *w = V + (size_t)j1 * ld;
+    cd *h1 = h->hbuf, *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
+    {
+        Timed tm(h, HELM_K_DOT, lev, 16.0 * (j1 + 1) * n);
+        HCHK(launch_mdot(V, ld, j1, w, n, h->part, 1, nullptr, 0, h->st));
+    }
+    HCHK(launch_reduce(h->part, nb, j1 + 1, h1, 0, nullptr, 0, h->sig, j1, nullptr, h->st));
+    {
+        Timed tm(h, HELM_K_UPDATE, lev, 16.0 * (j1 + 2) * n);
+        HCHK(launch_mupdate(w, V, ld, j1, h1, n, h->partn, nullptr, 0, h->sig, h->st));
+    }
+    HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
+    HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
+    HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
+    HCHK(launch_reduce(h->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, h->sig + j1, h->st));
+    HCHK(hipMemcpyAsync(h->hpin + slot * HBUF, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd),
+                        hipMemcpyDeviceToHost, h->st));
+    HCHK(hipEventRecord(h->ev_slot[slot], h->st));
+    return HELM_OK;
+}
+
+int arnoldi_finish(helm_ctx *h, int j1, int slot, zc *col, double *hn)
+{
+    HCHK(hipEventSynchronize(h->ev_slot[slot]));
+    const cd *hp = h->hpin + slot * HBUF;
+    bool reorth = false;
+    for (int i = 0; i < j1; i++) {
+        col[i] = zc(hp[i].x + hp[PSTRIDE + i].x, hp[i].y + hp[PSTRIDE + i].y);
+        reorth |= hp[PSTRIDE + i].x != 0.0 || hp[PSTRIDE + i].y != 0.0;
+    }
+    h->n_arnoldi++;
+    h->n_reorth += reorth;
+    *hn = hp[2 * PSTRIDE].x;
+    return HELM_OK;
+}
+
 int upload_y(helm_ctx *h, const std::vector<zc> &y)
 {
-    for (size_t i = 0; i < y.size(); i++) h->hpin[i] = make_double2(y[i].real(), y[i].imag());
-    HCHK(hipMemcpyAsync(h->ydev, h->hpin, y.size() * sizeof(cd), hipMemcpyHostToDevice, h->st));
+    for (size_t i = 0; i < y.size(); i++)
+        h->hpin[PIN_Y + i] = make_double2(y[i].real(), y[i].imag());
+    HCHK(hipMemcpyAsync(h->ydev, h->hpin + PIN_Y, y.size() * sizeof(cd), hipMemcpyHostToDevice,
+                        h->st));
     // the pinned staging buffer is reused by the next readback: wait for the copy
     HCHK(hipStreamSynchronize(h->st));
     return HELM_OK;
@@ -298,20 +355,27 @@ int apply_A(helm_ctx *h, int l, const cd *x, const cd *b, cd *y)
 
 // z (+)= V-cycle(r) starting on level l0; on level 0 the last pass may add
 // Z v2 (v2 on level 1).
-int vcycle(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2)
+int vcycle(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2,
+           const cd *rs = nullptr)
 {
     const int Lc = h->nlev - 1;
     if (l0 == Lc) {
-        HCHK(launch_coarsest(h->ncoarsest, h->cinv, r, accumulate ? h->L[Lc].x : z, h->st));
-        if (accumulate) HCHK(launch_lincomb(h->L[Lc].x, 0, 1, h->hbuf + 2 * PSTRIDE + 1, z,
-                                            h->L[Lc].n(), 1, h->st));
+        // the cycle is the exact coarsest solve; it is linear, so a right-hand
+        // side scale is applied to the result
+        if (!accumulate && !rs) {
+            HCHK(launch_coarsest(h->ncoarsest, h->cinv, r, z, h->st));
+            return HELM_OK;
+        }
+        HCHK(launch_coarsest(h->ncoarsest, h->cinv, r, h->L[Lc].x, h->st));
+        HCHK(launch_lincomb(h->L[Lc].x, 0, 1, rs ? rs : h->hbuf + 2 * PSTRIDE + 1, z,
+                            h->L[Lc].n(), accumulate, h->st));
         return HELM_OK;
     }
     const cd *rin = r;
     for (int l = l0; l < Lc; l++) {
         Timed tm(h, HELM_K_VC_DOWN, l, 16.0 * h->L[l].n() + 16.0 * h->L[l + 1].n());
-        HCHK(launch_vc_down(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, rin, h->L[l + 1].r,
-                            h->st));
+        HCHK(launch_vc_down(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, rin,
+                            l == l0 ? rs : nullptr, h->L[l + 1].r, h->st));
         rin = h->L[l + 1].r;
     }
     HCHK(launch_coarsest(h->ncoarsest, h->cinv, h->L[Lc].r, h->L[Lc].x, h->st));
@@ -323,8 +387,8 @@ int vcycle(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2
         const cd *vv = top ? v2 : nullptr;
         const double by = (32.0 + 16.0 * acc) * h->L[l].n() + 16.0 * h->L[l + 1].n() * (vv ? 2 : 1);
         Timed tm(h, HELM_K_VC_UP, l, by);
-        HCHK(launch_vc_up(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, rl, h->L[l + 1].x, out,
-                          acc, vv, h->zho, h->st));
+        HCHK(launch_vc_up(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, rl,
+                          top ? rs : nullptr, h->L[l + 1].x, out, acc, vv, h->zho, h->st));
     }
     return HELM_OK;
 }
@@ -346,10 +410,24 @@ int coarse_apply(helm_ctx *h, const cd *x, const cd *b, cd *y)
     return HELM_OK;
 }
 
+// One inner Arnoldi step j, enqueued: z = V(v_j), w = A_2h z written into
+// basis slot j+1, then the lazily normalised orthogonalisation.
+int inner_step_enqueue(helm_ctx *h, int j, int slot)
+{
+    const size_t nc = h->L[1].n();
+    RCHK(vcycle(h, 1, h->Vc + (size_t)j * nc, h->zc_, 0, nullptr, h->sig + j));
+    RCHK(coarse_apply(h, h->zc_, nullptr, h->Vc + (size_t)(j + 1) * nc));
+    return arnoldi_lazy_enqueue(h, h->Vc, nc, j + 1, nc, 1, slot);
+}
+
 // x ~= A_2h^{-1} b: right-preconditioned restarted GMRES, preconditioner = a
 // V-cycle starting on level 1, x0 = 0.  FIXED mode runs exactly coarse_iters
 // iterations; TOL mode stops at |g_{j+1}| <= coarse_tol ||b|| (checked on the
 // true residual at every restart) or at coarse_iters.
+// The host needs each step's Hessenberg column only to test convergence, so
+// step j+1 is enqueued before the host waits for step j: the GPU never idles
+// on the read-back.  A converged cycle leaves one speculative step, whose
+// results are not used.
 int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
 {
     const size_t nc = h->L[1].n();
@@ -360,50 +438,46 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
     int it = 0;
     if (iters) *iters = 0;
     double bnorm;
-    RCHK(vnorm(h, b, nc, &bnorm));
+    RCHK(vnorm(h, b, nc, &bnorm, h->sig));
     HCHK(launch_zero(x, nc, h->st));
     if (!std::isfinite(bnorm)) return HELM_ENONFINITE;
     if (bnorm == 0.0) return HELM_OK;
     Givens gv(m);
     std::vector<zc> col(m + 1), y;
+    std::vector<double> unorm(m + 1);
     bool first = true;
     for (;;) {
         double beta;
-        const cd *r;
         if (first) {
-            r = b;
-            beta = bnorm;
+            HCHK(hipMemcpyAsync(h->Vc, b, nc * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
+            beta = bnorm;  // sig[0] = 1/||b|| was stored by vnorm
         } else {
-            RCHK(coarse_apply(h, x, b, h->wc));
-            RCHK(vnorm(h, h->wc, nc, &beta));
-            r = h->wc;
+            RCHK(coarse_apply(h, x, b, h->Vc));
+            RCHK(vnorm(h, h->Vc, nc, &beta, h->sig));
         }
         if (!fixed && beta <= tol * bnorm) break;
         if (it >= cap || beta == 0.0) break;
-        // V_0 = r / beta (the norm is in the device slot written by vnorm)
-        HCHK(launch_scale(r, h->hbuf + 2 * PSTRIDE, h->Vc, nc, h->st));
         gv.start(beta);
+        unorm[0] = beta;
+        const int steps = std::min(m, cap - it);
         int jend = 0;
         bool stop = false;
-        for (int j = 0; j < m && it < cap; j++) {
-            cd *vj = h->Vc + (size_t)j * nc;
-            RCHK(vcycle(h, 1, vj, h->zc_, 0, nullptr));
-            RCHK(coarse_apply(h, h->zc_, nullptr, h->wc));
+        RCHK(inner_step_enqueue(h, 0, 0));
+        for (int j = 0; j < steps; j++) {
+            if (j + 1 < steps) RCHK(inner_step_enqueue(h, j + 1, (j + 1) & 1));
             double hn;
-            RCHK(arnoldi_step(h, h->Vc, nc, j + 1, h->wc, nc, col.data(), &hn, 1));
+            RCHK(arnoldi_finish(h, j + 1, j & 1, col.data(), &hn));
             const double res = gv.add_column(j, col.data(), hn);
             it++;
             jend = j + 1;
-            if (!fixed && res <= tol * bnorm) {
-                stop = true;
-                break;
-            }
-            if (hn == 0.0) {
+            unorm[j + 1] = hn;
+            if ((!fixed && res <= tol * bnorm) || hn == 0.0) {
                 stop = true;
                 break;
             }
         }
         gv.solve(jend, y);
+        for (int i = 0; i < jend; i++) y[i] /= unorm[i];  // v_i = u_i / ||u_i||
         RCHK(upload_y(h, y));
         HCHK(launch_lincomb(h->Vc, nc, jend, h->ydev, h->wc, nc, 0, h->st));
         RCHK(vcycle(h, 1, h->wc, x, 1, nullptr));
@@ -635,6 +709,9 @@ void release(helm_ctx *h)
     dfree(h->w);
     dfree(h->bm);
     if (h->hpin) (void)hipHostFree(h->hpin);
+    dfree(h->sig);
+    for (auto e : h->ev_slot)
+        if (e) (void)hipEventDestroy(e);
     for (auto &p : h->pend) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -666,6 +743,7 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
         return HELM_EINVAL;
     if (o.restart < 1 || o.restart > MAX_RESTART || o.maxit < 1) return HELM_EINVAL;
     if (!(o.tol >= 0) || !(o.coarse_tol >= 0)) return HELM_EINVAL;
+    if (o.coarsest_nodes < 0 || o.coarsest_nodes > MAX_COARSEST) return HELM_EINVAL;
     if (!k_dev && (!std::isfinite(k_const) || k_const < 0)) return HELM_ENONFINITE;
 
     helm_ctx *h = new (std::nothrow) helm_ctx();
@@ -689,6 +767,7 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
         q.hx = hx;
         q.hy = hy;
         if (!coarsenable(nx, ny) || h->nlev == MAXLEV) break;
+        if (h->nlev > 1 && (long)nx * (long)ny <= (long)o.coarsest_nodes) break;
         nx = (nx + 1) / 2;
         ny = (ny + 1) / 2;
         hx *= 2;
@@ -745,10 +824,16 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (!rc) rc = dalloc(&h->partn, (size_t)h->part_blocks * PSTRIDE);
     if (!rc) rc = dalloc(&h->hbuf, (size_t)HBUF);
     if (!rc) rc = dalloc(&h->ydev, (size_t)PSTRIDE);
-    if (!rc && hipHostMalloc((void **)&h->hpin, HBUF * sizeof(cd)) != hipSuccess) {
+    if (!rc) rc = dalloc(&h->sig, (size_t)PSTRIDE);
+    if (!rc && hipHostMalloc((void **)&h->hpin, PIN_TOTAL * sizeof(cd)) != hipSuccess) {
         h->hpin = nullptr;
         rc = HELM_ENOMEM;
     }
+    for (int q = 0; q < 2 && !rc; q++)
+        if (hipEventCreateWithFlags(&h->ev_slot[q], hipEventDisableTiming) != hipSuccess) {
+            h->ev_slot[q] = nullptr;
+            rc = HELM_EHIP;
+        }
     if (!rc) {
         // slot 2*PSTRIDE+1 holds the constant 1 used to accumulate on the
         // coarsest level
@@ -793,6 +878,7 @@ int helm_opts_default(helm_opts *o)
     o->tol = 1e-6;
     o->x0_given = 0;
     o->force_iters = 0;
+    o->coarsest_nodes = 1089;
     return HELM_OK;
 }
 

@@ -154,77 +154,149 @@ hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hi
 }
 
 // ------------------------------------------------------------------------
+// Per-node smoother coefficients.  With a constant wavenumber every node that
+// is not on the grid boundary has the same diagonal, so the kernels take
+// ap and omega/ap for those nodes as launch constants (no division per node);
+// boundary nodes (Sommerfeld closure) and variable-k levels use coef5.
+// Dirichlet boundary nodes are not unknowns and hold 0 in the LDS tiles, so
+// the interior constants are exact for their unknown neighbours too.
+// ------------------------------------------------------------------------
+struct Smooth {
+    double apr, api;  // interior diagonal (constant k)
+    double wr, wi;    // omega / diagonal
+};
+
+Smooth smooth_consts(const Lev &L, cd s, double omega)
+{
+    Smooth c;
+    const double k2 = L.kc * L.kc;
+    c.apr = 2.0 * L.ihx2 + 2.0 * L.ihy2 - s.x * k2;
+    c.api = -s.y * k2;
+    const double d = omega / (c.apr * c.apr + c.api * c.api);
+    c.wr = c.apr * d;
+    c.wi = -c.api * d;
+    return c;
+}
+
+// Coefficients of node (i,j) (inside the grid).  Returns false for a
+// non-unknown node.  winv = omega / ap.
+template <bool VARK>
+__device__ __forceinline__ bool node_coef(const Lev &L, cd s, double omega, const Smooth &c,
+                                          int i, int j, cd &ap, cd &winv, double &aw,
+                                          double &ae, double &as, double &an)
+{
+    const bool edge = i == 0 || j == 0 || i == L.nx - 1 || j == L.ny - 1;
+    if (!VARK && !edge) {
+        ap = make_double2(c.apr, c.api);
+        winv = make_double2(c.wr, c.wi);
+        aw = ae = -L.ihx2;
+        as = an = -L.ihy2;
+        return true;
+    }
+    if (!coef5(L, s, i, j, ap, aw, ae, as, an)) return false;
+    winv = cscal(omega, cinv(ap));
+    return true;
+}
+
+// ------------------------------------------------------------------------
 // V-cycle, downward pass on a level (fused):
 //   x1 = omega D^{-1} r            (one damped-Jacobi sweep from x = 0)
 //   r1 = r - M x1                  (residual)
 //   rc = full weighting of r1      (1/16 [1 2 1; 2 4 2; 1 2 1], truncated)
-// One block computes a 32 x 8 tile of coarse nodes; x1 lives in LDS on the
-// 67 x 19 fine region it needs, r1 on the inner 65 x 17 region.
+// One block computes a 32 x 8 tile of coarse nodes from the 67 x 19 fine
+// region it needs: r and x1 live in LDS, r1 overwrites r in place.
 // ------------------------------------------------------------------------
 constexpr int VD_CX = 32, VD_CY = 8;
 constexpr int VD_X1W = 2 * VD_CX + 3, VD_X1H = 2 * VD_CY + 3;  // 67 x 19
-constexpr int VD_R1W = 2 * VD_CX + 1, VD_R1H = 2 * VD_CY + 1;  // 65 x 17
 
-__global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double omega,
-                                                 const cd *__restrict__ r, cd *__restrict__ rc,
+template <bool VARK>
+__global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double omega, Smooth c,
+                                                 const cd *__restrict__ r,
+                                                 const cd *__restrict__ rs, cd *__restrict__ rc,
                                                  int tiles_x)
 {
+    const double rsc = rs ? rs[0].x : 1.0;  // right-hand side = rsc * r
     __shared__ cd sx1[VD_X1H][VD_X1W];
-    __shared__ cd sr1[VD_R1H][VD_R1W];
+    __shared__ cd sr[VD_X1H][VD_X1W];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int I0 = (t % tiles_x) * VD_CX, J0 = (t / tiles_x) * VD_CY;
     const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
-    for (int q = threadIdx.x; q < VD_X1W * VD_X1H; q += 256) {
+    // all global loads first (unconditional, from a valid address), so that
+    // they are in flight together; then the arithmetic
+    constexpr int NQ = VD_X1W * VD_X1H, NK = (NQ + 255) / 256;
+    cd rl[NK];
+#pragma unroll
+    for (int kq = 0; kq < NK; kq++) {
+        const int q = threadIdx.x + 256 * kq;
         const int a = q % VD_X1W, bb = q / VD_X1W;
         const int fi = fi0 + a, fj = fj0 + bb;
-        cd v = czero();
-        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
-            cd ap;
-            double aw, ae, as, an;
-            if (coef5(Lf, s, fi, fj, ap, aw, ae, as, an))
-                v = cscal(omega, cmul(cinv(ap), r[(size_t)fj * Lf.nx + fi]));
+        const bool in = q < NQ && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny;
+        const cd v = r[in ? (size_t)fj * Lf.nx + fi : 0];
+        rl[kq] = in ? v : czero();
+    }
+#pragma unroll
+    for (int kq = 0; kq < NK; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        if (q < NQ) {
+            const int a = q % VD_X1W, bb = q / VD_X1W;
+            const int fi = fi0 + a, fj = fj0 + bb;
+            cd v = czero(), rv = czero();
+            if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
+                cd ap, wv;
+                double aw, ae, as, an;
+                if (node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an)) {
+                    rv = rs ? cscal(rsc, rl[kq]) : rl[kq];
+                    v = cmul(wv, rv);
+                }
+            }
+            sx1[bb][a] = v;
+            sr[bb][a] = rv;
         }
-        sx1[bb][a] = v;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < VD_R1W * VD_R1H; q += 256) {
-        const int a = q % VD_R1W, bb = q / VD_R1W;
-        const int fi = fi0 + 1 + a, fj = fj0 + 1 + bb;
-        cd v = czero();
+#pragma unroll
+    for (int kq = 0; kq < ((VD_X1W - 2) * (VD_X1H - 2) + 255) / 256; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        if (q >= (VD_X1W - 2) * (VD_X1H - 2)) continue;
+        const int a = q % (VD_X1W - 2) + 1, bb = q / (VD_X1W - 2) + 1;
+        const int fi = fi0 + a, fj = fj0 + bb;
         if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
-            cd ap;
+            cd ap, wv;
             double aw, ae, as, an;
-            if (coef5(Lf, s, fi, fj, ap, aw, ae, as, an)) {
-                cd m = cmul(ap, sx1[bb + 1][a + 1]);
-                caxpy(m, aw, sx1[bb + 1][a]);
-                caxpy(m, ae, sx1[bb + 1][a + 2]);
-                caxpy(m, as, sx1[bb][a + 1]);
-                caxpy(m, an, sx1[bb + 2][a + 1]);
-                v = csub(r[(size_t)fj * Lf.nx + fi], m);
+            if (node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an)) {
+                cd m = cmul(ap, sx1[bb][a]);
+                caxpy(m, aw, sx1[bb][a - 1]);
+                caxpy(m, ae, sx1[bb][a + 1]);
+                caxpy(m, as, sx1[bb - 1][a]);
+                caxpy(m, an, sx1[bb + 1][a]);
+                sr[bb][a] = csub(sr[bb][a], m);
             }
         }
-        sr1[bb][a] = v;
     }
     __syncthreads();
     const int I = I0 + (threadIdx.x % VD_CX), J = J0 + (threadIdx.x / VD_CX);
     if (I >= Lc.nx || J >= Lc.ny) return;
     cd v = czero();
     if (unknown(Lc, I, J)) {
-        const int a = 2 * (I - I0) + 1, bb = 2 * (J - J0) + 1;
-        cd c = cscal(4.0, sr1[bb][a]);
-        cd e = cadd(cadd(sr1[bb][a - 1], sr1[bb][a + 1]), cadd(sr1[bb - 1][a], sr1[bb + 1][a]));
-        cd d = cadd(cadd(sr1[bb - 1][a - 1], sr1[bb - 1][a + 1]),
-                    cadd(sr1[bb + 1][a - 1], sr1[bb + 1][a + 1]));
-        v = cscal(1.0 / 16.0, cadd(cadd(c, cscal(2.0, e)), d));
+        const int a = 2 * (I - I0) + 2, bb = 2 * (J - J0) + 2;
+        cd ce = cscal(4.0, sr[bb][a]);
+        cd e = cadd(cadd(sr[bb][a - 1], sr[bb][a + 1]), cadd(sr[bb - 1][a], sr[bb + 1][a]));
+        cd d = cadd(cadd(sr[bb - 1][a - 1], sr[bb - 1][a + 1]),
+                    cadd(sr[bb + 1][a - 1], sr[bb + 1][a + 1]));
+        v = cscal(1.0 / 16.0, cadd(cadd(ce, cscal(2.0, e)), d));
     }
     rc[(size_t)J * Lc.nx + I] = v;
 }
 
-hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r, cd *rc,
-                          hipStream_t st)
+hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
+                          const cd *rs, cd *rc, hipStream_t st)
 {
     const int tx = cdiv(Lc.nx, VD_CX), ty = cdiv(Lc.ny, VD_CY);
-    k_vc_down<<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, r, rc, tx);
+    const Smooth c = smooth_consts(Lf, s, omega);
+    if (Lf.k)
+        k_vc_down<true><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx);
+    else
+        k_vc_down<false><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx);
     HD_LAUNCH_CHECK();
 }
 
@@ -234,30 +306,82 @@ hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, cons
 //                                    plus the bilinear coarse correction)
 //   x3 = x2 + omega D^{-1} (r - M x2)   (post-smoothing sweep)
 //   out = x3 [+ Z v2] [+ out]
-// One block writes a 64 x 16 fine tile; x2 lives in LDS on 66 x 18.
+// One block writes a 64 x 16 fine tile.  r (66 x 18), the coarse correction
+// tile (34 x 10) and x2 (66 x 18) live in LDS.
 // ------------------------------------------------------------------------
 constexpr int VU_TX = 64, VU_TY = 16;
 constexpr int VU_W = VU_TX + 2, VU_H = VU_TY + 2;
+constexpr int VU_CW = VU_TX / 2 + 2, VU_CH = VU_TY / 2 + 2;  // 34 x 10
 
-__global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omega,
+template <bool VARK>
+__global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omega, Smooth c,
                                                const cd *__restrict__ r,
+                                               const cd *__restrict__ rs,
                                                const cd *__restrict__ ec, cd *__restrict__ out,
                                                int accumulate, const cd *__restrict__ v2,
                                                int zho, int tiles_x)
 {
+    const double rsc = rs ? rs[0].x : 1.0;  // right-hand side = rsc * r
     __shared__ cd sx2[VU_H][VU_W];
+    __shared__ cd sr[VU_H][VU_W];
+    __shared__ cd se[VU_CH][VU_CW];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i0 = (t % tiles_x) * VU_TX, j0 = (t / tiles_x) * VU_TY;
-    for (int q = threadIdx.x; q < VU_W * VU_H; q += 256) {
+    const int ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // coarse tile origin
+    constexpr int NC = VU_CW * VU_CH, NKC = (NC + 255) / 256;
+    constexpr int NQ = VU_W * VU_H, NK = (NQ + 255) / 256;
+    cd el[NKC], rl[NK];
+    // all global loads first (unconditional, from a valid address)
+#pragma unroll
+    for (int kq = 0; kq < NKC; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        const int I = ci0 + q % VU_CW, J = cj0 + q / VU_CW;
+        const bool in = q < NC && I >= 0 && I < Lc.nx && J >= 0 && J < Lc.ny && unknown(Lc, I, J);
+        const cd v = ec[in ? (size_t)J * Lc.nx + I : 0];
+        el[kq] = in ? v : czero();
+    }
+#pragma unroll
+    for (int kq = 0; kq < NK; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        const int fi = i0 - 1 + q % VU_W, fj = j0 - 1 + q / VU_W;
+        const bool in = q < NQ && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny &&
+                        unknown(Lf, fi, fj);
+        const cd v = r[in ? (size_t)fj * Lf.nx + fi : 0];
+        rl[kq] = in ? (rs ? cscal(rsc, v) : v) : czero();
+    }
+#pragma unroll
+    for (int kq = 0; kq < NKC; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        if (q < NC) se[q / VU_CW][q % VU_CW] = el[kq];
+    }
+#pragma unroll
+    for (int kq = 0; kq < NK; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        if (q < NQ) sr[q / VU_W][q % VU_W] = rl[kq];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kq = 0; kq < NK; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        if (q >= NQ) continue;
         const int a = q % VU_W, bb = q / VU_W;
         const int fi = i0 - 1 + a, fj = j0 - 1 + bb;
         cd v = czero();
         if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
-            cd ap;
+            cd ap, wv;
             double aw, ae, as, an;
-            if (coef5(Lf, s, fi, fj, ap, aw, ae, as, an)) {
-                v = cscal(omega, cmul(cinv(ap), r[(size_t)fj * Lf.nx + fi]));
-                v = cadd(v, prolong_at(Lc, ec, fi, fj, 0));
+            if (node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an)) {
+                // bilinear interpolation from the coarse tile: coarse node
+                // (fi >> 1, fj >> 1) sits at se[(fj >> 1) - cj0][(fi >> 1) - ci0]
+                const int ca = (fi >> 1) - ci0, cb = (fj >> 1) - cj0;
+                cd p = se[cb][ca];
+                if (fi & 1) p = cscal(0.5, cadd(p, se[cb][ca + 1]));
+                if (fj & 1) {
+                    cd p2 = se[cb + 1][ca];
+                    if (fi & 1) p2 = cscal(0.5, cadd(p2, se[cb + 1][ca + 1]));
+                    p = cscal(0.5, cadd(p, p2));
+                }
+                v = cadd(cmul(wv, sr[bb][a]), p);
             }
         }
         sx2[bb][a] = v;
@@ -272,16 +396,16 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
         if (j >= Lf.ny) break;
         const int a = i - i0 + 1, bb = jl + 1;
         const size_t p = (size_t)j * Lf.nx + i;
-        cd ap;
+        cd ap, wv;
         double aw, ae, as, an;
         cd v = czero();
-        if (coef5(Lf, s, i, j, ap, aw, ae, as, an)) {
+        if (node_coef<VARK>(Lf, s, omega, c, i, j, ap, wv, aw, ae, as, an)) {
             cd m = cmul(ap, sx2[bb][a]);
             caxpy(m, aw, sx2[bb][a - 1]);
             caxpy(m, ae, sx2[bb][a + 1]);
             caxpy(m, as, sx2[bb - 1][a]);
             caxpy(m, an, sx2[bb + 1][a]);
-            v = cadd(sx2[bb][a], cscal(omega, cmul(cinv(ap), csub(r[p], m))));
+            v = cadd(sx2[bb][a], cmul(wv, csub(sr[bb][a], m)));
             if (v2) v = cadd(v, prolong_at(Lc, v2, i, j, zho));
         }
         if (accumulate) v = cadd(v, out[p]);
@@ -290,31 +414,57 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
 }
 
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
-                        const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
+                        const cd *rs, const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
                         hipStream_t st)
 {
     const int tx = cdiv(Lf.nx, VU_TX), ty = cdiv(Lf.ny, VU_TY);
-    k_vc_up<<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, r, ec, out, accumulate, v2, zho, tx);
+    const Smooth c = smooth_consts(Lf, s, omega);
+    if (Lf.k)
+        k_vc_up<true><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out, accumulate, v2,
+                                               zho, tx);
+    else
+        k_vc_up<false><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out, accumulate, v2,
+                                                zho, tx);
     HD_LAUNCH_CHECK();
 }
 
 // ------------------------------------------------------------------------
-// Coarsest level: x = Minv r (dense precomputed inverse, one row per thread)
+// Coarsest level: x = Minv r with the precomputed dense inverse.  One wave per
+// row: the lanes stride along the row (coalesced) and reduce by shuffles.
 // ------------------------------------------------------------------------
+__device__ __forceinline__ cd wave_sum64(cd v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(256) void k_coarsest(int n, const cd *__restrict__ Minv,
                                                   const cd *__restrict__ r, cd *__restrict__ x)
 {
-    const int row = blockIdx.x * 256 + threadIdx.x;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (row >= n) return;
-    cd s = czero();
+    cd s0 = czero(), s1 = czero(), s2 = czero(), s3 = czero();
     const cd *m = Minv + (size_t)row * n;
-    for (int c = 0; c < n; c++) s = cadd(s, cmul(m[c], r[c]));
-    x[row] = s;
+    int c = lane;
+    for (; c + 192 < n; c += 256) {
+        s0 = cadd(s0, cmul(m[c], r[c]));
+        s1 = cadd(s1, cmul(m[c + 64], r[c + 64]));
+        s2 = cadd(s2, cmul(m[c + 128], r[c + 128]));
+        s3 = cadd(s3, cmul(m[c + 192], r[c + 192]));
+    }
+    for (; c < n; c += 64) s0 = cadd(s0, cmul(m[c], r[c]));
+    cd s = wave_sum64(cadd(cadd(s0, s1), cadd(s2, s3)));
+    if (lane == 0) x[row] = s;
 }
 
 hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st)
 {
-    k_coarsest<<<cdiv(n, 256), 256, 0, st>>>(n, Minv, r, x);
+    k_coarsest<<<cdiv(n, 4), 256, 0, st>>>(n, Minv, r, x);
     HD_LAUNCH_CHECK();
 }
 
@@ -337,7 +487,10 @@ __global__ __launch_bounds__(256) void k_zt(Lev Lf, Lev Lc, int zho, const cd *_
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int I0 = (t % tiles_x) * ZT_CX, J0 = (t / tiles_x) * ZT_CY;
     const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
-    for (int q = threadIdx.x; q < ZT_W * ZT_H; q += 256) {
+#pragma unroll
+    for (int kq = 0; kq < (ZT_W * ZT_H + 255) / 256; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        if (q >= ZT_W * ZT_H) continue;
         const int a = q % ZT_W, bb = q / ZT_W;
         const int fi = fi0 + a, fj = fj0 + bb;
         cd v = czero();
@@ -347,7 +500,10 @@ __global__ __launch_bounds__(256) void k_zt(Lev Lf, Lev Lc, int zho, const cd *_
     }
     __syncthreads();
     const double w0 = zho ? 0.75 : 1.0, w1 = 0.5, w2 = zho ? 0.125 : 0.0;
-    for (int q = threadIdx.x; q < ZT_CX * ZT_H; q += 256) {
+#pragma unroll
+    for (int kq = 0; kq < (ZT_CX * ZT_H + 255) / 256; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        if (q >= ZT_CX * ZT_H) continue;
         const int c = q % ZT_CX, bb = q / ZT_CX;
         const int a = 2 * c + 2;
         cd v = cscal(w0, sv[bb][a]);
@@ -415,7 +571,10 @@ __global__ __launch_bounds__(256) void k_dresid(Lev Lf, Lev Lc, int zho,
     __shared__ cd sz[VU_H][VU_W];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i0 = (t % tiles_x) * VU_TX, j0 = (t / tiles_x) * VU_TY;
-    for (int q = threadIdx.x; q < VU_W * VU_H; q += 256) {
+#pragma unroll
+    for (int kq = 0; kq < (VU_W * VU_H + 255) / 256; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        if (q >= VU_W * VU_H) continue;
         const int a = q % VU_W, bb = q / VU_W;
         const int fi = i0 - 1 + a, fj = j0 - 1 + bb;
         cd z = czero();
@@ -468,7 +627,7 @@ hipError_t launch_dresid(const Lev &Lf, const Lev &Lc, int zho, const cd *v, con
 //   k^2 part   = WX (x) WY applied to (k^2 u), k taken at each stencil node;
 // these reproduce the printed stencils (1/256)[...]/(2h)^2 and k^2/64^2 [...].
 // Each thread streams one column over 16 rows, keeping the x-filtered rows in
-// registers.  Boundary rows are done by k_redglk2_band.
+// registers.  Boundary rows are done by redglk2_band in the same launch.
 // ------------------------------------------------------------------------
 __constant__ double c_L1[5] = {-6.0 / 16, -8.0 / 16, 28.0 / 16, -8.0 / 16, -6.0 / 16};
 __constant__ double c_W1[5] = {1.0 / 64, 28.0 / 64, 70.0 / 64, 28.0 / 64, 1.0 / 64};
@@ -476,11 +635,11 @@ __constant__ double c_W1[5] = {1.0 / 64, 28.0 / 64, 70.0 / 64, 28.0 / 64, 1.0 / 
 constexpr int RG_TX = 64, RG_RPW = 16;  // 64 columns x (4 waves x 16 rows)
 
 template <bool RESID, bool VARK>
-__global__ __launch_bounds__(256) void k_redglk2_int(Lev L, const cd *__restrict__ u,
-                                                     const cd *__restrict__ b,
-                                                     cd *__restrict__ y, int tiles_x)
+__device__ __forceinline__ void redglk2_interior(const Lev &L, const cd *__restrict__ u,
+                                                 const cd *__restrict__ b, cd *__restrict__ y,
+                                                 int tiles_x, int nb_int)
 {
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = xcd_tile(blockIdx.x, nb_int);
     const int I = (t % tiles_x) * RG_TX + (threadIdx.x & 63);
     const int J0 = (t / tiles_x) * (4 * RG_RPW) + (threadIdx.x >> 6) * RG_RPW;
     if (I < 2 || I > L.nx - 3) return;
@@ -584,17 +743,16 @@ __device__ __forceinline__ cd ghost_y(const Lev &L, const cd *u, int I, int Jg)
 // = the 5x5 stencil with ghost nodes eliminated (k = 0 at ghosts; a ghost
 // outside in both directions is the mean of its two single-direction
 // neighbours).  Dirichlet boundary nodes are not unknowns.
-template <bool RESID>
 // Band layout: nR boundary-band rows (0, 1, ny-2, ny-1 without repeats; all
 // rows when ny < 5) cover every column; then nC band columns cover the rows
 // 2..ny-3 in between.  Band row k is k for k < 2, else ny - nR + k (columns
-// alike).
-__global__ __launch_bounds__(256) void k_redglk2_band(Lev L, const cd *__restrict__ u,
-                                                      const cd *__restrict__ b,
-                                                      cd *__restrict__ y, int nR, int nC,
-                                                      int count)
+// alike).  blk numbers the band's own blocks.
+template <bool RESID>
+__device__ __forceinline__ void redglk2_band(const Lev &L, const cd *__restrict__ u,
+                                             const cd *__restrict__ b, cd *__restrict__ y,
+                                             int nR, int nC, int count, int blk)
 {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const int idx = blk * 256 + threadIdx.x;
     if (idx >= count) return;
     int I, J;
     if (idx < nR * L.nx) {
@@ -647,34 +805,43 @@ __global__ __launch_bounds__(256) void k_redglk2_band(Lev L, const cd *__restric
     y[p] = o;
 }
 
+// One launch for the whole coarse operator: blocks [0, nb_int) do interior
+// tiles, the blocks after them the boundary band, so both run concurrently.
+template <bool RESID, bool VARK>
+__global__ __launch_bounds__(256) void k_redglk2(Lev L, const cd *__restrict__ u,
+                                                 const cd *__restrict__ b, cd *__restrict__ y,
+                                                 int tiles_x, int nb_int, int nR, int nC,
+                                                 int count)
+{
+    if ((int)blockIdx.x < nb_int)
+        redglk2_interior<RESID, VARK>(L, u, b, y, tiles_x, nb_int);
+    else
+        redglk2_band<RESID>(L, u, b, y, nR, nC, count, blockIdx.x - nb_int);
+}
+
 hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, hipStream_t st)
 {
-    // interior
+    int tx = 0, nb_int = 0;
     if (L.nx >= 5 && L.ny >= 5) {
-        const int tx = cdiv(L.nx, RG_TX), ty = cdiv(L.ny, 4 * RG_RPW);
-        const int nb = tx * ty;
-        if (L.k) {
-            if (b)
-                k_redglk2_int<true, true><<<nb, 256, 0, st>>>(L, x, b, y, tx);
-            else
-                k_redglk2_int<false, true><<<nb, 256, 0, st>>>(L, x, b, y, tx);
-        } else {
-            if (b)
-                k_redglk2_int<true, false><<<nb, 256, 0, st>>>(L, x, b, y, tx);
-            else
-                k_redglk2_int<false, false><<<nb, 256, 0, st>>>(L, x, b, y, tx);
-        }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        tx = cdiv(L.nx, RG_TX);
+        nb_int = tx * cdiv(L.ny, 4 * RG_RPW);
     }
     // band: rows {0,1,ny-2,ny-1} and columns {0,1,nx-2,nx-1} without repeats
     const int nR = L.ny < 4 ? L.ny : 4, nC = L.nx < 4 ? L.nx : 4;
     const int inner_rows = L.ny - nR;  // rows 2..ny-3 when ny >= 5, else 0
     const int count = nR * L.nx + nC * inner_rows;
-    if (b)
-        k_redglk2_band<true><<<cdiv(count, 256), 256, 0, st>>>(L, x, b, y, nR, nC, count);
-    else
-        k_redglk2_band<false><<<cdiv(count, 256), 256, 0, st>>>(L, x, b, y, nR, nC, count);
+    const int nb = nb_int + cdiv(count, 256);
+    if (L.k) {
+        if (b)
+            k_redglk2<true, true><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
+        else
+            k_redglk2<false, true><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
+    } else {
+        if (b)
+            k_redglk2<true, false><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
+        else
+            k_redglk2<false, false><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
+    }
     HD_LAUNCH_CHECK();
 }
 
@@ -694,7 +861,8 @@ __global__ void k_mdot(const cd *__restrict__ V, size_t ld, int m, const cd *__r
                        const cd *__restrict__ cond, int jcond);
 __global__ void k_mupdate(cd *__restrict__ w, const cd *__restrict__ V, size_t ld, int m,
                           const cd *__restrict__ c, size_t n, size_t chunk,
-                          cd *__restrict__ partn, const cd *__restrict__ cond, int jcond);
+                          cd *__restrict__ partn, const cd *__restrict__ cond, int jcond,
+                          const cd *__restrict__ sig);
 
 static int resident_blocks()
 {
@@ -834,12 +1002,14 @@ hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd 
     HD_LAUNCH_CHECK();
 }
 
-// w -= sum_i c_i V_i over the block's chunk; partn[blk] = |w_new|^2 partial
-// (if partn).  cond: second pass, skipped unless need_reorth(cond, jcond).
+// w -= sum_i c_i sig_i V_i over the block's chunk (sig_i = 1 without sig);
+// partn[blk] = |w_new|^2 partial (if partn).  cond: second pass, skipped
+// unless need_reorth(cond, jcond).
 __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *__restrict__ V,
                                                  size_t ld, int m, const cd *__restrict__ c,
                                                  size_t n, size_t chunk, cd *__restrict__ partn,
-                                                 const cd *__restrict__ cond, int jcond)
+                                                 const cd *__restrict__ cond, int jcond,
+                                                 const cd *__restrict__ sig)
 {
     if (cond && !need_reorth(cond, jcond)) return;
     __shared__ cd red[4];
@@ -851,7 +1021,11 @@ __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *_
     for (int s = 0; s < KR_S; s++) acc[s] = czero();
     int i = 0;
     for (; i + 1 < m; i += 2) {
-        const cd c0 = c[i], c1 = c[i + 1];
+        cd c0 = c[i], c1 = c[i + 1];
+        if (sig) {
+            c0 = cscal(sig[i].x, c0);
+            c1 = cscal(sig[i + 1].x, c1);
+        }
         const cd *v0 = V + (size_t)i * ld, *v1 = V + (size_t)(i + 1) * ld;
 #pragma unroll
         for (int s = 0; s < KR_S; s++) {
@@ -866,7 +1040,8 @@ __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *_
         }
     }
     if (i < m) {
-        const cd c0 = c[i];
+        cd c0 = c[i];
+        if (sig) c0 = cscal(sig[i].x, c0);
         const cd *v0 = V + (size_t)i * ld;
 #pragma unroll
         for (int s = 0; s < KR_S; s++) {
@@ -898,19 +1073,24 @@ __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *_
 }
 
 hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *partn,
-                          const cd *cond, int jcond, hipStream_t st)
+                          const cd *cond, int jcond, const cd *sig, hipStream_t st)
 {
     const int nb = krylov_blocks(n);
-    k_mupdate<<<nb, 256, 0, st>>>(w, V, ld, m, c, n, krylov_chunk(n, nb), partn, cond, jcond);
+    k_mupdate<<<nb, 256, 0, st>>>(w, V, ld, m, c, n, krylov_chunk(n, nb), partn, cond, jcond,
+                                  sig);
     HD_LAUNCH_CHECK();
 }
 
-// out[i] = sum over blocks of part[blk][i] (fixed tree order); mode 0 store,
-// 1 accumulate, 2 store sqrt(real part).  cond: second-pass reduction, which
-// stores zeros unless need_reorth(cond, jcond).
+// out[i] = sum over blocks of part[blk][i] (fixed tree order); mode 0 store
+// (times sig[i] for i < nsig when sig is given), 1 accumulate, 2 store
+// sqrt(real part) into out[0] and, if sig_out, its reciprocal (0 for a zero
+// norm) into sig_out[0].  cond: second-pass reduction, which stores zeros
+// unless need_reorth(cond, jcond).
 __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int nblk,
                                                 cd *__restrict__ out, int mode,
-                                                const cd *__restrict__ cond, int jcond)
+                                                const cd *__restrict__ cond, int jcond,
+                                                const cd *__restrict__ sig, int nsig,
+                                                cd *__restrict__ sig_out)
 {
     __shared__ cd red[256];
     const int i = blockIdx.x;
@@ -927,20 +1107,24 @@ __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const cd v = red[0];
-        if (mode == 0)
+        cd v = red[0];
+        if (mode == 0) {
+            if (sig && i < nsig) v = cscal(sig[i].x, v);
             out[i] = v;
-        else if (mode == 1)
+        } else if (mode == 1) {
             out[i] = cadd(out[i], v);
-        else
-            out[i] = make_double2(sqrt(v.x), 0.0);
+        } else {
+            const double nr = sqrt(v.x);
+            out[i] = make_double2(nr, 0.0);
+            if (sig_out) sig_out[0] = make_double2(nr > 0.0 ? 1.0 / nr : 0.0, 0.0);
+        }
     }
 }
 
 hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, const cd *cond,
-                         int jcond, hipStream_t st)
+                         int jcond, const cd *sig, int nsig, cd *sig_out, hipStream_t st)
 {
-    k_reduce<<<m, 256, 0, st>>>(part, nblk, out, mode, cond, jcond);
+    k_reduce<<<m, 256, 0, st>>>(part, nblk, out, mode, cond, jcond, sig, nsig, sig_out);
     HD_LAUNCH_CHECK();
 }
 

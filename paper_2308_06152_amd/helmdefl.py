@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
                 ("coarse_mode", ctypes.c_int), ("coarse_iters", ctypes.c_int),
                 ("coarse_restart", ctypes.c_int), ("coarse_tol", ctypes.c_double),
                 ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("tol", ctypes.c_double),
-                ("x0_given", ctypes.c_int), ("force_iters", ctypes.c_int)]
+                ("x0_given", ctypes.c_int), ("force_iters", ctypes.c_int),
+                ("coarsest_nodes", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

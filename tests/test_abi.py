@@ -46,6 +46,7 @@ def test_defaults_and_strerror(H):
     assert (o.beta_re, o.beta_im, o.omega, o.nu_pre, o.nu_post) == (1.0, 0.5, 0.8, 1, 1)
     assert (o.restart, o.tol, o.coarse_tol, o.coarse_restart) == (50, 1e-6, 0.1, 30)
     assert o.defl_vectors == H.Z_HIGH
+    assert o.coarsest_nodes == 1089
     L = H.load()
     assert L.helm_strerror(0) == b"success"
     assert b"coarsen" in L.helm_strerror(H.HELM_EGRID)
@@ -69,7 +70,8 @@ def test_create_rejects_uncoarsenable_grids(H, nx, ny):
 @pytest.mark.parametrize("kw", [dict(nu_pre=2), dict(nu_post=0), dict(restart=0),
                                 dict(restart=61), dict(coarse_restart=0), dict(coarse_iters=0),
                                 dict(coarse_mode=0), dict(coarse_op=7), dict(defl_vectors=3),
-                                dict(omega=0.0), dict(tol=-1.0)])
+                                dict(omega=0.0), dict(tol=-1.0), dict(coarsest_nodes=-1),
+                                dict(coarsest_nodes=5000)])
 def test_create_rejects_bad_options(H, kw):
     assert _create(H, 9, 9, **kw) == H.HELM_EINVAL
 

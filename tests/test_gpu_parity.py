@@ -63,7 +63,7 @@ CASES = [
 ]
 
 
-def make_pair(H, ora, case, **kw):
+def make_pair(H, ora, case, coarsest_nodes=1089, **kw):
     name, nx, ny, bc, kind, kv, cop = case
     h = 1.0 / (max(nx, ny) - 1)
     if kind == "const":
@@ -72,7 +72,8 @@ def make_pair(H, ora, case, **kw):
         kfield, kconst = inputs.random_field(ny, nx, kv[0], kv[1], seed=nx * 7 + ny), 0.0
     okw = dict(coarse_op=cop)
     okw.update(kw)
-    P = ora.Problem(nx, ny, h, h, bc=bc, k=kfield, kconst=kconst, **{
+    P = ora.Problem(nx, ny, h, h, bc=bc, k=kfield, kconst=kconst, coarsest_nodes=coarsest_nodes,
+                    **{
         k2: v for k2, v in okw.items() if k2 in ("coarse_op", "defl_vectors", "coarse_restart",
                                                   "coarse_tol", "beta_re", "beta_im", "omega")})
     gkw = {k2: v for k2, v in okw.items() if k2 in ("coarse_op", "defl_vectors", "coarse_restart",
@@ -80,7 +81,7 @@ def make_pair(H, ora, case, **kw):
                                                       "coarse_mode", "coarse_iters", "restart",
                                                       "tol", "maxit", "force_iters")}
     kt = dev(kfield) if kfield is not None else None
-    S = H.Solver(nx, ny, h, h, bc, k=kt, kconst=kconst, **gkw)
+    S = H.Solver(nx, ny, h, h, bc, k=kt, kconst=kconst, coarsest_nodes=coarsest_nodes, **gkw)
     return S, P
 
 
@@ -97,9 +98,11 @@ def test_helm_apply_parity(H, ora, case):
     assert rel(got2[1], ora.helm_apply(P, x2[1])) <= 1e-12
 
 
+@pytest.mark.parametrize("coarsest", [0, 1089, 289])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_vcycle_parity(H, ora, case):
-    S, P = make_pair(H, ora, case)
+def test_vcycle_parity(H, ora, case, coarsest):
+    S, P = make_pair(H, ora, case, coarsest_nodes=coarsest)
+    assert S.num_levels() == ora.num_levels(P.nx, P.ny, coarsest)
     r = inputs.random_complex((P.ny, P.nx), 103)
     got = host(S.vcycle(dev(r)))
     want = ora.vcycle(P, r)
@@ -174,6 +177,7 @@ def _solve_pair(H, ora, w, **kw):
     okw.update(kw)
     S = H.Solver(w.nx, w.ny, h, h, w.bc, kconst=w.kconst, **okw)
     P = ora.Problem(w.nx, w.ny, h, h, bc=w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+                    coarsest_nodes=S.opts.coarsest_nodes,
                     coarse_mode=ora.CMODE_TOL if okw["coarse_mode"] == 2 else ora.CMODE_FIXED,
                     coarse_tol=okw["coarse_tol"], coarse_iters=okw["coarse_iters"],
                     coarse_restart=okw["coarse_restart"])

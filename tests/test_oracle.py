@@ -513,8 +513,31 @@ def test_paper_iteration_counts(ora, row):
     assert inf.converged and abs(inf.iters - paper) <= 1, (inf.iters, paper)
 
 
+def test_vcycle_with_predefined_coarsest_grid(ora):
+    """Section 4: coarsening stops at a predefined coarsest grid that is solved
+    directly.  With the coarsest grid equal to the first coarse level the
+    cycle is a two-grid cycle; both variants stay textbook multigrid for k = 0
+    and the deeper cycle is not better than the two-grid one."""
+    n = 65
+    rates = {}
+    for cn in (0, 1089, 1088):
+        p = _prob(ora, n, 0.0, 0, coarsest_nodes=cn)
+        e = _interior(inputs.random_complex((n, n), 7))
+        norms = []
+        for _ in range(7):
+            e = e + ora.vcycle(p, -ora.helm_apply(p, e))
+            norms.append(np.linalg.norm(e))
+        rates[cn] = norms[-1] / norms[-2]
+    assert all(0.2 < r < 0.45 for r in rates.values()), rates
+    assert rates[1089] <= rates[0] * 1.001
+    assert ora.num_levels(65, 65, 1089) == 2      # 65 -> 33 (33^2 = 1089: stop)
+    assert ora.num_levels(65, 65, 1088) == 3 and ora.level_dims(65, 65, 2, 1088) == (17, 17)
+
+
 def test_level_hierarchy(ora):
     assert ora.num_levels(129, 129) == 7
+    assert ora.num_levels(129, 129, 1089) == 3  # 129 -> 65 -> 33
+    assert ora.num_levels(33, 33, 1089) == 2    # level 1 always exists
     assert ora.level_dims(129, 129, 6) == (3, 3)
     assert ora.num_levels(4097, 4097) == 12
     assert ora.num_levels(37, 53) == 3  # 37x53 -> 19x27 -> 10x14 (even: stop)
