@@ -215,74 +215,98 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
                                                  const cd *__restrict__ rs, cd *__restrict__ rc,
                                                  int tiles_x)
 {
+    // Thread (cx, cy) computes coarse node (I0+cx, J0+cy) and owns the 2 x 2
+    // fine nodes (2I+dx, 2J+dy), keeping r and then r1 there in registers.
+    // One LDS tile (67 x 19, local (a, b) = fine (2*I0-2+a, 2*J0-2+b)) holds
+    // x1, then is reused for r1.  The 249 halo nodes of the tile are spread
+    // one per thread; those on the r1 ring (a == 1 or b == 1) also get r1.
     const double rsc = rs ? rs[0].x : 1.0;  // right-hand side = rsc * r
-    __shared__ cd sx1[VD_X1H][VD_X1W];
-    __shared__ cd sr[VD_X1H][VD_X1W];
+    __shared__ cd st[VD_X1H][VD_X1W];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int I0 = (t % tiles_x) * VD_CX, J0 = (t / tiles_x) * VD_CY;
     const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
-    // all global loads first (unconditional, from a valid address), so that
-    // they are in flight together; then the arithmetic
-    constexpr int NQ = VD_X1W * VD_X1H, NK = (NQ + 255) / 256;
-    cd rl[NK];
+    const int cx = threadIdx.x % VD_CX, cy = threadIdx.x / VD_CX;
+    // halo node of this thread
+    int ha = -1, hb = -1;
+    {
+        const int q = threadIdx.x;
+        if (q < 3 * VD_X1H) {
+            const int col = q / VD_X1H;
+            ha = col == 0 ? 0 : (col == 1 ? 1 : VD_X1W - 1);
+            hb = q % VD_X1H;
+        } else if (q < 3 * VD_X1H + 3 * 2 * VD_CX) {
+            const int qq = q - 3 * VD_X1H, row = qq / (2 * VD_CX);
+            hb = row == 0 ? 0 : (row == 1 ? 1 : VD_X1H - 1);
+            ha = 2 + qq % (2 * VD_CX);
+        }
+    }
+    // ---- global loads (unconditional, from a valid address)
+    cd rown[4], rhalo;
 #pragma unroll
-    for (int kq = 0; kq < NK; kq++) {
-        const int q = threadIdx.x + 256 * kq;
-        const int a = q % VD_X1W, bb = q / VD_X1W;
-        const int fi = fi0 + a, fj = fj0 + bb;
-        const bool in = q < NQ && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny;
+    for (int d = 0; d < 4; d++) {
+        const int fi = fi0 + 2 + 2 * cx + (d & 1), fj = fj0 + 2 + 2 * cy + (d >> 1);
+        const bool in = fi < Lf.nx && fj < Lf.ny;
         const cd v = r[in ? (size_t)fj * Lf.nx + fi : 0];
-        rl[kq] = in ? v : czero();
+        rown[d] = in ? (rs ? cscal(rsc, v) : v) : czero();
     }
-#pragma unroll
-    for (int kq = 0; kq < NK; kq++) {
-        const int q = threadIdx.x + 256 * kq;
-        if (q < NQ) {
-            const int a = q % VD_X1W, bb = q / VD_X1W;
-            const int fi = fi0 + a, fj = fj0 + bb;
-            cd v = czero(), rv = czero();
-            if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
-                cd ap, wv;
-                double aw, ae, as, an;
-                if (node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an)) {
-                    rv = rs ? cscal(rsc, rl[kq]) : rl[kq];
-                    v = cmul(wv, rv);
-                }
-            }
-            sx1[bb][a] = v;
-            sr[bb][a] = rv;
+    {
+        const int fi = fi0 + ha, fj = fj0 + hb;
+        const bool in = ha >= 0 && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny;
+        const cd v = r[in ? (size_t)fj * Lf.nx + fi : 0];
+        rhalo = in ? (rs ? cscal(rsc, v) : v) : czero();
+    }
+    // r at non-unknown nodes (Dirichlet boundary) and outside the grid is 0
+    auto x1_at = [&](int fi, int fj, cd &rv) -> cd {
+        cd ap, wv;
+        double aw, ae, as, an;
+        if (fi < 0 || fi >= Lf.nx || fj < 0 || fj >= Lf.ny ||
+            !node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an)) {
+            rv = czero();
+            return czero();
         }
-    }
+        return cmul(wv, rv);
+    };
+#pragma unroll
+    for (int d = 0; d < 4; d++)
+        st[2 + 2 * cy + (d >> 1)][2 + 2 * cx + (d & 1)] =
+            x1_at(fi0 + 2 + 2 * cx + (d & 1), fj0 + 2 + 2 * cy + (d >> 1), rown[d]);
+    if (ha >= 0) st[hb][ha] = x1_at(fi0 + ha, fj0 + hb, rhalo);
+    __syncthreads();
+    // ---- r1 = r - M x1 at the owned nodes and the r1 ring
+    auto r1_at = [&](int a, int b, cd rv) -> cd {
+        const int fi = fi0 + a, fj = fj0 + b;
+        cd ap, wv;
+        double aw, ae, as, an;
+        if (fi < 0 || fi >= Lf.nx || fj < 0 || fj >= Lf.ny ||
+            !node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
+            return czero();
+        cd m = cmul(ap, st[b][a]);
+        caxpy(m, aw, st[b][a - 1]);
+        caxpy(m, ae, st[b][a + 1]);
+        caxpy(m, as, st[b - 1][a]);
+        caxpy(m, an, st[b + 1][a]);
+        return csub(rv, m);
+    };
+    cd r1own[4], r1halo = czero();
+#pragma unroll
+    for (int d = 0; d < 4; d++) r1own[d] = r1_at(2 + 2 * cx + (d & 1), 2 + 2 * cy + (d >> 1), rown[d]);
+    const bool ring = ha >= 1 && ha <= VD_X1W - 2 && hb >= 1 && hb <= VD_X1H - 2;
+    if (ring) r1halo = r1_at(ha, hb, rhalo);
     __syncthreads();
 #pragma unroll
-    for (int kq = 0; kq < ((VD_X1W - 2) * (VD_X1H - 2) + 255) / 256; kq++) {
-        const int q = threadIdx.x + 256 * kq;
-        if (q >= (VD_X1W - 2) * (VD_X1H - 2)) continue;
-        const int a = q % (VD_X1W - 2) + 1, bb = q / (VD_X1W - 2) + 1;
-        const int fi = fi0 + a, fj = fj0 + bb;
-        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
-            cd ap, wv;
-            double aw, ae, as, an;
-            if (node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an)) {
-                cd m = cmul(ap, sx1[bb][a]);
-                caxpy(m, aw, sx1[bb][a - 1]);
-                caxpy(m, ae, sx1[bb][a + 1]);
-                caxpy(m, as, sx1[bb - 1][a]);
-                caxpy(m, an, sx1[bb + 1][a]);
-                sr[bb][a] = csub(sr[bb][a], m);
-            }
-        }
-    }
+    for (int d = 0; d < 4; d++) st[2 + 2 * cy + (d >> 1)][2 + 2 * cx + (d & 1)] = r1own[d];
+    if (ring) st[hb][ha] = r1halo;
     __syncthreads();
-    const int I = I0 + (threadIdx.x % VD_CX), J = J0 + (threadIdx.x / VD_CX);
+    // ---- full weighting around fine node (2I, 2J) = local (2cx+2, 2cy+2)
+    const int I = I0 + cx, J = J0 + cy;
     if (I >= Lc.nx || J >= Lc.ny) return;
     cd v = czero();
     if (unknown(Lc, I, J)) {
-        const int a = 2 * (I - I0) + 2, bb = 2 * (J - J0) + 2;
-        cd ce = cscal(4.0, sr[bb][a]);
-        cd e = cadd(cadd(sr[bb][a - 1], sr[bb][a + 1]), cadd(sr[bb - 1][a], sr[bb + 1][a]));
-        cd d = cadd(cadd(sr[bb - 1][a - 1], sr[bb - 1][a + 1]),
-                    cadd(sr[bb + 1][a - 1], sr[bb + 1][a + 1]));
+        const int a = 2 * cx + 2, bb = 2 * cy + 2;
+        cd ce = cscal(4.0, st[bb][a]);
+        cd e = cadd(cadd(st[bb][a - 1], st[bb][a + 1]), cadd(st[bb - 1][a], st[bb + 1][a]));
+        cd d = cadd(cadd(st[bb - 1][a - 1], st[bb - 1][a + 1]),
+                    cadd(st[bb + 1][a - 1], st[bb + 1][a + 1]));
         v = cscal(1.0 / 16.0, cadd(cadd(ce, cscal(2.0, e)), d));
     }
     rc[(size_t)J * Lc.nx + I] = v;
@@ -321,17 +345,38 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
                                                int accumulate, const cd *__restrict__ v2,
                                                int zho, int tiles_x)
 {
+    // Thread (tx, ty) owns output column tx and rows 4*ty .. 4*ty+3 of the
+    // 64 x 16 tile and keeps r there in registers; x2 (66 x 18 with its
+    // one-node halo) and the coarse correction tile (34 x 10) live in LDS.
     const double rsc = rs ? rs[0].x : 1.0;  // right-hand side = rsc * r
     __shared__ cd sx2[VU_H][VU_W];
-    __shared__ cd sr[VU_H][VU_W];
     __shared__ cd se[VU_CH][VU_CW];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i0 = (t % tiles_x) * VU_TX, j0 = (t / tiles_x) * VU_TY;
     const int ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // coarse tile origin
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     constexpr int NC = VU_CW * VU_CH, NKC = (NC + 255) / 256;
-    constexpr int NQ = VU_W * VU_H, NK = (NQ + 255) / 256;
-    cd el[NKC], rl[NK];
-    // all global loads first (unconditional, from a valid address)
+    constexpr int NHALO = 2 * VU_H + 2 * VU_TX;  // 164 halo nodes of the x2 tile
+    // the halo node of this thread (threads >= NHALO have none)
+    int ha = -1, hb = -1;
+    {
+        const int q = threadIdx.x;
+        if (q < VU_H) {
+            ha = 0;
+            hb = q;
+        } else if (q < 2 * VU_H) {
+            ha = VU_W - 1;
+            hb = q - VU_H;
+        } else if (q < 2 * VU_H + VU_TX) {
+            ha = q - 2 * VU_H + 1;
+            hb = 0;
+        } else if (q < NHALO) {
+            ha = q - 2 * VU_H - VU_TX + 1;
+            hb = VU_H - 1;
+        }
+    }
+    // ---- all global loads first (unconditional, from a valid address)
+    cd el[NKC], rown[4], rhalo;
 #pragma unroll
     for (int kq = 0; kq < NKC; kq++) {
         const int q = threadIdx.x + 256 * kq;
@@ -340,61 +385,61 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
         const cd v = ec[in ? (size_t)J * Lc.nx + I : 0];
         el[kq] = in ? v : czero();
     }
+    const int i = i0 + tx;
 #pragma unroll
-    for (int kq = 0; kq < NK; kq++) {
-        const int q = threadIdx.x + 256 * kq;
-        const int fi = i0 - 1 + q % VU_W, fj = j0 - 1 + q / VU_W;
-        const bool in = q < NQ && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny &&
+    for (int rr = 0; rr < 4; rr++) {
+        const int j = j0 + 4 * ty + rr;
+        const bool in = i < Lf.nx && j < Lf.ny && unknown(Lf, i, j);
+        const cd v = r[in ? (size_t)j * Lf.nx + i : 0];
+        rown[rr] = in ? (rs ? cscal(rsc, v) : v) : czero();
+    }
+    {
+        const int fi = i0 - 1 + ha, fj = j0 - 1 + hb;
+        const bool in = ha >= 0 && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny &&
                         unknown(Lf, fi, fj);
         const cd v = r[in ? (size_t)fj * Lf.nx + fi : 0];
-        rl[kq] = in ? (rs ? cscal(rsc, v) : v) : czero();
+        rhalo = in ? (rs ? cscal(rsc, v) : v) : czero();
     }
 #pragma unroll
     for (int kq = 0; kq < NKC; kq++) {
         const int q = threadIdx.x + 256 * kq;
         if (q < NC) se[q / VU_CW][q % VU_CW] = el[kq];
     }
-#pragma unroll
-    for (int kq = 0; kq < NK; kq++) {
-        const int q = threadIdx.x + 256 * kq;
-        if (q < NQ) sr[q / VU_W][q % VU_W] = rl[kq];
-    }
     __syncthreads();
-#pragma unroll
-    for (int kq = 0; kq < NK; kq++) {
-        const int q = threadIdx.x + 256 * kq;
-        if (q >= NQ) continue;
-        const int a = q % VU_W, bb = q / VU_W;
-        const int fi = i0 - 1 + a, fj = j0 - 1 + bb;
-        cd v = czero();
-        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny) {
-            cd ap, wv;
-            double aw, ae, as, an;
-            if (node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an)) {
-                // bilinear interpolation from the coarse tile: coarse node
-                // (fi >> 1, fj >> 1) sits at se[(fj >> 1) - cj0][(fi >> 1) - ci0]
-                const int ca = (fi >> 1) - ci0, cb = (fj >> 1) - cj0;
-                cd p = se[cb][ca];
-                if (fi & 1) p = cscal(0.5, cadd(p, se[cb][ca + 1]));
-                if (fj & 1) {
-                    cd p2 = se[cb + 1][ca];
-                    if (fi & 1) p2 = cscal(0.5, cadd(p2, se[cb + 1][ca + 1]));
-                    p = cscal(0.5, cadd(p, p2));
-                }
-                v = cadd(cmul(wv, sr[bb][a]), p);
-            }
+    // ---- x2 = omega D^-1 r + P ec at the owned nodes and the halo node
+    auto x2_at = [&](int fi, int fj, cd rv) -> cd {
+        cd ap, wv;
+        double aw, ae, as, an;
+        if (fi < 0 || fi >= Lf.nx || fj < 0 || fj >= Lf.ny ||
+            !node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
+            return czero();
+        // bilinear interpolation from the coarse tile: coarse node
+        // (fi >> 1, fj >> 1) sits at se[(fj >> 1) - cj0][(fi >> 1) - ci0]
+        const int ca = (fi >> 1) - ci0, cb = (fj >> 1) - cj0;
+        cd p = se[cb][ca];
+        if (fi & 1) p = cscal(0.5, cadd(p, se[cb][ca + 1]));
+        if (fj & 1) {
+            cd p2 = se[cb + 1][ca];
+            if (fi & 1) p2 = cscal(0.5, cadd(p2, se[cb + 1][ca + 1]));
+            p = cscal(0.5, cadd(p, p2));
         }
-        sx2[bb][a] = v;
+        return cadd(cmul(wv, rv), p);
+    };
+#pragma unroll
+    for (int rr = 0; rr < 4; rr++) {
+        const int jl = 4 * ty + rr;
+        sx2[jl + 1][tx + 1] = x2_at(i, j0 + jl, rown[rr]);
     }
+    if (ha >= 0) sx2[hb][ha] = x2_at(i0 - 1 + ha, j0 - 1 + hb, rhalo);
     __syncthreads();
-    const int i = i0 + (threadIdx.x & 63);
+    // ---- post-smoothing at the owned nodes
     if (i >= Lf.nx) return;
 #pragma unroll
-    for (int rr = 0; rr < VU_TY / 4; rr++) {
-        const int jl = (threadIdx.x >> 6) * (VU_TY / 4) + rr;
+    for (int rr = 0; rr < 4; rr++) {
+        const int jl = 4 * ty + rr;
         const int j = j0 + jl;
         if (j >= Lf.ny) break;
-        const int a = i - i0 + 1, bb = jl + 1;
+        const int a = tx + 1, bb = jl + 1;
         const size_t p = (size_t)j * Lf.nx + i;
         cd ap, wv;
         double aw, ae, as, an;
@@ -405,7 +450,7 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
             caxpy(m, ae, sx2[bb][a + 1]);
             caxpy(m, as, sx2[bb - 1][a]);
             caxpy(m, an, sx2[bb + 1][a]);
-            v = cadd(sx2[bb][a], cmul(wv, csub(sr[bb][a], m)));
+            v = cadd(sx2[bb][a], cmul(wv, csub(rown[rr], m)));
             if (v2) v = cadd(v, prolong_at(Lc, v2, i, j, zho));
         }
         if (accumulate) v = cadd(v, out[p]);
