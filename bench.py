@@ -36,7 +36,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--workload", choices=["large", "small", "wedge"], default="large",
+                    help="large: 4097^2 k=800 Sommerfeld (the headline); small: 129^2 "
+                         "Dirichlet k=20; wedge: the 1153 x 1921 three-layer model at 40 Hz")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="mixed: complex64 fine-grid V-cycle inside the FP64 solve")
     ap.add_argument("--roofline-kernel", default="mdot",
                     help="kernel class whose roofline is reported")
     ap.add_argument("--roofline-level", type=int, default=1,
@@ -84,7 +88,8 @@ def cpu_baseline(w, info, coarsest_nodes):
     import oracle
     from paper_2308_06152_amd import inputs
     oracle.build(force=False)
-    P = oracle.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+    P = oracle.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, k=w.kfield(), kconst=w.kconst,
+                       coarse_op=w.coarse_op,
                        coarse_mode=oracle.CMODE_FIXED, coarse_iters=1,
                        coarse_restart=w.coarse_restart, coarsest_nodes=coarsest_nodes)
     nxc, nyc = oracle.coarse_dims(P)
@@ -140,10 +145,15 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    w = inputs.large_plain() if a.workload == "large" else inputs.small_plain()
-    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
-                 coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol, coarse_iters=w.coarse_maxit,
-                 coarse_restart=w.coarse_restart, restart=w.restart, tol=w.tol)
+    w = {"large": inputs.large_plain, "small": inputs.small_plain,
+         "wedge": inputs.wedge}[a.workload]()
+    kf = w.kfield()
+    prec = H.PREC_MIXED if a.precision == "mixed" else H.PREC_FP64
+    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc,
+                 k=None if kf is None else torch.from_numpy(kf).cuda(), kconst=w.kconst,
+                 coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
+                 coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart, restart=w.restart,
+                 tol=w.tol, precision=prec)
     b = torch.from_numpy(w.rhs()).cuda()
     x = torch.zeros_like(b)
     torch.cuda.synchronize()
@@ -167,7 +177,7 @@ def main():
         print("bench.py: a solve did not converge", file=sys.stderr)
         sys.exit(1)
     achieved = (k_bytes / 1e9) / (k_ms / 1e3) if k_ms > 0 else 0.0
-    traffic = measured_traffic(a.roofline_kernel, w.name)
+    traffic = measured_traffic(a.roofline_kernel, w.name) if prec == H.PREC_FP64 else None
     line = {
         "metric": METRIC,
         "value": a.steps / elapsed,
@@ -179,14 +189,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == H.PREC_FP64 else "f64 (f32 fine-grid V-cycle)",
         "data": "synthetic",
         "config": {
-            "workload": w.name, "grid": f"{w.nx}x{w.ny}", "k": w.kconst,
+            "workload": w.name + ("_mixed" if prec == H.PREC_MIXED else ""),
+            "grid": f"{w.nx}x{w.ny}",
+            "k": w.kconst if kf is None else f"wedge model at {w.freq:g} Hz",
             "bc": "sommerfeld" if w.bc == H.BC_SOMMERFELD else "dirichlet",
             "source": "gaussian sigma=2h" if w.source == "gauss" else "point",
             "preconditioner": "APD (Bezier Z, " + ("ReD-Glk2" if w.coarse_op else "Galerkin")
-                              + " A_2h) + 1 CSLP V-cycle (1,0.5)",
+                              + " A_2h) + 1 CSLP V-cycle (1,0.5)"
+                              + (" in complex64" if prec == H.PREC_MIXED else ""),
             "krylov": f"FGMRES({w.restart}) to {w.tol:g}",
             "coarse_solve": f"GMRES({w.coarse_restart}) to {w.coarse_tol:g}",
             "outer_iters": last["outer_iters"], "inner_iters_total": last["inner_iters_total"],

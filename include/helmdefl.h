@@ -53,6 +53,7 @@ enum { HELM_DEFL_Q = 0, HELM_DEFL_P = 1, HELM_DEFL_ADEF1 = 2 };
 enum { HELM_Z_LINEAR = 0, HELM_Z_HIGH = 1 };
 enum { HELM_COARSE_GALERKIN = 0, HELM_COARSE_REDGLK2 = 1 };
 enum { HELM_CMODE_FIXED = 1, HELM_CMODE_TOL = 2 };
+enum { HELM_PREC_FP64 = 0, HELM_PREC_MIXED = 1 };
 
 /* The grid: nx x ny vertex nodes including the boundary, spacings hx, hy
  * (Section 2.1 takes hx = hy = h; ReD-Glk2 requires hx == hy). */
@@ -83,6 +84,15 @@ typedef struct {
                                 <= this many nodes; that level is solved exactly
                                 (default 1089 = 33 x 33; 0 = down to 3 x 3;
                                 at most 2048) */
+    int precision;           /* HELM_PREC_FP64 (default): everything in FP64.
+                                HELM_PREC_MIXED: the fine-grid CSLP V-cycle
+                                (cslp_vcycle, and M^{-1} inside A-DEF1) runs in
+                                complex64 on every level: it reads r in FP64,
+                                stores the levels in FP32 and writes z in FP64.
+                                The Krylov methods, A_h, the deflation (with its
+                                coarse GMRES and that solve's own V-cycle) and
+                                the residual test stay FP64; FGMRES absorbs the
+                                perturbed preconditioner (Section 5.2). */
 } helm_opts;
 
 /* Per right-hand side result of helm_solve. */
@@ -125,7 +135,9 @@ int helm_apply(helm_ctx *h, const void *x, void *y, int nrhs);
 /* z = V(r): one CSLP multigrid V-cycle (Sections 3.1 and 5.1) for
  * M = -Lap - (beta_re + i beta_im) k^2, re-discretised on every level with the
  * injected wavenumber; 1 damped-Jacobi pre- and post-sweep from x = 0, full
- * weighting, bilinear interpolation, exact solve on the coarsest level. */
+ * weighting, bilinear interpolation, exact solve on the coarsest level.
+ * With opts.precision == HELM_PREC_MIXED the cycle computes in complex64
+ * (r and z stay complex128 in memory). */
 int cslp_vcycle(helm_ctx *h, const void *r, void *z, int nrhs);
 
 /* Deflation applied to v (Sections 3.2.2 and 5.2): with v1 = Z^T v,

@@ -1,6 +1,7 @@
 // hd_common.h -- types and launch wrappers shared by the HIP kernels and the
 // host driver of libhelmdefl.so (gfx950).  Complex128 values are double2
-// (x = real, y = imaginary), 16-byte aligned, interleaved as in the C-ABI.
+// (x = real, y = imaginary), 16-byte aligned, interleaved as in the C-ABI;
+// complex64 values (the mixed-precision V-cycle) are float2.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,6 +10,7 @@
 namespace hd {
 
 typedef double2 cd;
+typedef float2 cf;
 
 enum { BC_DIR = 0, BC_SOM = 1 };
 
@@ -113,8 +115,22 @@ hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, cons
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
                         const cd *rs, const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
                         hipStream_t st);
+// Mixed-precision V-cycle (complex64 arithmetic and level storage): the top
+// level reads r in FP64 and writes rc in FP32, and its upward pass reads r in
+// FP64, ec in FP32 and writes out in FP64 (adding Z v2 in FP64); levels below
+// are FP32 throughout.
+hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r, cf *rc,
+                          hipStream_t st);
+hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r, cf *rc,
+                          hipStream_t st);
+hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
+                        const cf *ec, cd *out, int accumulate, const cd *v2, int zho,
+                        hipStream_t st);
+hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
+                        const cf *ec, cf *out, hipStream_t st);
 // x = Minv r on the coarsest level (dense inverse, n x n, row major).
 hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st);
+hipError_t launch_coarsest(int n, const cf *Minv, const cf *r, cf *x, hipStream_t st);
 // vc = Z^T vf, or vc = b - Z^T vf when b != nullptr.
 hipError_t launch_zt(const Lev &Lf, const Lev &Lc, int zho, const cd *vf, const cd *b, cd *vc,
                      hipStream_t st);

@@ -47,6 +47,8 @@ struct LevelH {
     double *kdev = nullptr;  // per-level wavenumber (nullptr: constant)
     cd *r = nullptr;         // V-cycle right-hand side on this level (l >= 1)
     cd *x = nullptr;         // V-cycle correction on this level (l >= 1)
+    cf *rf = nullptr;        // complex64 twins for the mixed-precision cycle
+    cf *xf = nullptr;
     size_t n() const { return (size_t)nx * (size_t)ny; }
 };
 
@@ -115,6 +117,7 @@ struct helm_ctx {
 
     // coarsest level dense inverse
     cd *cinv = nullptr;
+    cf *cinvf = nullptr;  // its FP32 rounding (mixed precision)
     int ncoarsest = 0;
 
     // deflation workspace (coarse grid = level 1)
@@ -353,12 +356,46 @@ int apply_A(helm_ctx *h, int l, const cd *x, const cd *b, cd *y)
     return HELM_OK;
 }
 
+// z (+)= V-cycle(r) from level 0 in complex64: FP64 r in, FP32 levels, FP64 z
+// out (with Z v2 added in FP64).
+int vcycle_mixed(helm_ctx *h, const cd *r, cd *z, int accumulate, const cd *v2)
+{
+    const int Lc = h->nlev - 1;
+    for (int l = 0; l < Lc; l++) {
+        const double by = (l == 0 ? 16.0 : 8.0) * h->L[l].n() + 8.0 * h->L[l + 1].n();
+        Timed tm(h, HELM_K_VC_DOWN, l, by);
+        if (l == 0)
+            HCHK(launch_vc_down(h->lev(0), h->lev(1), h->shift, h->o.omega, r, h->L[1].rf, h->st));
+        else
+            HCHK(launch_vc_down(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, h->L[l].rf,
+                                h->L[l + 1].rf, h->st));
+    }
+    HCHK(launch_coarsest(h->ncoarsest, h->cinvf, h->L[Lc].rf, h->L[Lc].xf, h->st));
+    for (int l = Lc - 1; l >= 0; l--) {
+        if (l == 0) {
+            const double by = (32.0 + 16.0 * accumulate) * h->L[0].n() + 8.0 * h->L[1].n() +
+                              (v2 ? 16.0 * h->L[1].n() : 0.0);
+            Timed tm(h, HELM_K_VC_UP, 0, by);
+            HCHK(launch_vc_up(h->lev(0), h->lev(1), h->shift, h->o.omega, r, h->L[1].xf, z,
+                              accumulate, v2, h->zho, h->st));
+        } else {
+            Timed tm(h, HELM_K_VC_UP, l, 16.0 * h->L[l].n() + 8.0 * h->L[l + 1].n());
+            HCHK(launch_vc_up(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, h->L[l].rf,
+                              h->L[l + 1].xf, h->L[l].xf, h->st));
+        }
+    }
+    return HELM_OK;
+}
+
 // z (+)= V-cycle(r) starting on level l0; on level 0 the last pass may add
-// Z v2 (v2 on level 1).
+// Z v2 (v2 on level 1).  From level 0 with the mixed-precision option the
+// cycle runs in complex64.
 int vcycle(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2,
            const cd *rs = nullptr)
 {
     const int Lc = h->nlev - 1;
+    if (l0 == 0 && h->o.precision == HELM_PREC_MIXED && !rs)
+        return vcycle_mixed(h, r, z, accumulate, v2);
     if (l0 == Lc) {
         // the cycle is the exact coarsest solve; it is linear, so a right-hand
         // side scale is applied to the result
@@ -677,6 +714,13 @@ int setup_coarsest(helm_ctx *h, const std::vector<std::vector<double>> &khost)
         }
     RCHK(dalloc(&h->cinv, (size_t)n * n));
     HCHK(hipMemcpy(h->cinv, inv.data(), inv.size() * sizeof(cd), hipMemcpyHostToDevice));
+    if (h->o.precision == HELM_PREC_MIXED) {
+        std::vector<cf> invf(inv.size());
+        for (size_t q = 0; q < inv.size(); q++)
+            invf[q] = make_float2((float)inv[q].x, (float)inv[q].y);
+        RCHK(dalloc(&h->cinvf, invf.size()));
+        HCHK(hipMemcpy(h->cinvf, invf.data(), invf.size() * sizeof(cf), hipMemcpyHostToDevice));
+    }
     h->ncoarsest = n;
     return HELM_OK;
 }
@@ -689,8 +733,11 @@ void release(helm_ctx *h)
         dfree(h->L[l].kdev);
         dfree(h->L[l].r);
         dfree(h->L[l].x);
+        dfree(h->L[l].rf);
+        dfree(h->L[l].xf);
     }
     dfree(h->cinv);
+    dfree(h->cinvf);
     dfree(h->v1);
     dfree(h->v2);
     dfree(h->tf);
@@ -744,6 +791,7 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (o.restart < 1 || o.restart > MAX_RESTART || o.maxit < 1) return HELM_EINVAL;
     if (!(o.tol >= 0) || !(o.coarse_tol >= 0)) return HELM_EINVAL;
     if (o.coarsest_nodes < 0 || o.coarsest_nodes > MAX_COARSEST) return HELM_EINVAL;
+    if (o.precision != HELM_PREC_FP64 && o.precision != HELM_PREC_MIXED) return HELM_EINVAL;
     if (!k_dev && (!std::isfinite(k_const) || k_const < 0)) return HELM_ENONFINITE;
 
     helm_ctx *h = new (std::nothrow) helm_ctx();
@@ -805,6 +853,8 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     for (int l = 1; l < h->nlev && !rc; l++) {
         rc = dalloc(&h->L[l].r, h->L[l].n());
         if (!rc) rc = dalloc(&h->L[l].x, h->L[l].n());
+        if (!rc && o.precision == HELM_PREC_MIXED) rc = dalloc(&h->L[l].rf, h->L[l].n());
+        if (!rc && o.precision == HELM_PREC_MIXED) rc = dalloc(&h->L[l].xf, h->L[l].n());
     }
     if (!rc) rc = setup_coarsest(h, kh);
     // deflation and inner-GMRES workspace
@@ -879,6 +929,7 @@ int helm_opts_default(helm_opts *o)
     o->x0_given = 0;
     o->force_iters = 0;
     o->coarsest_nodes = 1089;
+    o->precision = HELM_PREC_FP64;
     return HELM_OK;
 }
 

@@ -15,6 +15,8 @@
 //    tree in a second kernel.
 #include "hd_common.h"
 
+#include <type_traits>
+
 namespace hd {
 
 #define HD_LAUNCH_CHECK() return hipGetLastError()
@@ -41,6 +43,32 @@ __device__ __forceinline__ void caxpy(cd &a, double s, cd b)
     a.x = fma(s, b.x, a.x);
     a.y = fma(s, b.y, a.y);
 }
+
+// The same helpers for complex64 (float2), and the precision-generic names
+// used by the kernels templated on the real type R (double or float).
+__device__ __forceinline__ cf cadd(cf a, cf b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cf csub(cf a, cf b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cf cscal(float s, cf a) { return make_float2(s * a.x, s * a.y); }
+__device__ __forceinline__ cf cmul(cf a, cf b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ void caxpy(cf &a, float s, cf b)
+{
+    a.x = fmaf(s, b.x, a.x);
+    a.y = fmaf(s, b.y, a.y);
+}
+template <class R> struct CxT;
+template <> struct CxT<double> { typedef cd T; };
+template <> struct CxT<float> { typedef cf T; };
+template <class R> using cx = typename CxT<R>::T;
+template <class R> __device__ __forceinline__ cx<R> mkc(R a, R b);
+template <> __device__ __forceinline__ cd mkc<double>(double a, double b) { return make_double2(a, b); }
+template <> __device__ __forceinline__ cf mkc<float>(float a, float b) { return make_float2(a, b); }
+template <class R> __device__ __forceinline__ cx<R> zc() { return mkc<R>((R)0, (R)0); }
+// conversion (rounding to nearest) between the two complex types
+template <class R> __device__ __forceinline__ cx<R> cvt(cd a) { return mkc<R>((R)a.x, (R)a.y); }
+template <class R> __device__ __forceinline__ cx<R> cvt(cf a) { return mkc<R>((R)a.x, (R)a.y); }
 
 // Map hardware block id to a logical tile id so that each of the 8 XCDs
 // (which receive block ids round-robin) works on a contiguous range of tiles.
@@ -157,44 +185,63 @@ hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hi
 // Per-node smoother coefficients.  With a constant wavenumber every node that
 // is not on the grid boundary has the same diagonal, so the kernels take
 // ap and omega/ap for those nodes as launch constants (no division per node);
-// boundary nodes (Sommerfeld closure) and variable-k levels use coef5.
+// boundary nodes (Sommerfeld closure) and variable-k levels use coef5, always
+// evaluated in FP64 and then rounded to the working precision R.
 // Dirichlet boundary nodes are not unknowns and hold 0 in the LDS tiles, so
 // the interior constants are exact for their unknown neighbours too.
 // ------------------------------------------------------------------------
+template <class R>
 struct Smooth {
-    double apr, api;  // interior diagonal (constant k)
-    double wr, wi;    // omega / diagonal
+    R apr, api;  // interior diagonal (constant k)
+    R wr, wi;    // omega / diagonal
+    R ax, ay;    // interior off-diagonals -1/hx^2, -1/hy^2
 };
 
-Smooth smooth_consts(const Lev &L, cd s, double omega)
+template <class R>
+Smooth<R> smooth_consts(const Lev &L, cd s, double omega)
 {
-    Smooth c;
     const double k2 = L.kc * L.kc;
-    c.apr = 2.0 * L.ihx2 + 2.0 * L.ihy2 - s.x * k2;
-    c.api = -s.y * k2;
-    const double d = omega / (c.apr * c.apr + c.api * c.api);
-    c.wr = c.apr * d;
-    c.wi = -c.api * d;
+    const double apr = 2.0 * L.ihx2 + 2.0 * L.ihy2 - s.x * k2, api = -s.y * k2;
+    const double d = omega / (apr * apr + api * api);
+    Smooth<R> c;
+    c.apr = (R)apr;
+    c.api = (R)api;
+    c.wr = (R)(apr * d);
+    c.wi = (R)(-api * d);
+    c.ax = (R)(-L.ihx2);
+    c.ay = (R)(-L.ihy2);
     return c;
 }
 
-// Coefficients of node (i,j) (inside the grid).  Returns false for a
-// non-unknown node.  winv = omega / ap.
-template <bool VARK>
-__device__ __forceinline__ bool node_coef(const Lev &L, cd s, double omega, const Smooth &c,
-                                          int i, int j, cd &ap, cd &winv, double &aw,
-                                          double &ae, double &as, double &an)
+// Coefficients of node (i,j) (inside the grid) in precision R.  Returns false
+// for a non-unknown node.  winv = omega / ap.
+template <bool VARK, class R>
+__device__ __forceinline__ bool node_coef(const Lev &L, cd s, double omega, const Smooth<R> &c,
+                                          int i, int j, cx<R> &ap, cx<R> &winv, R &aw, R &ae,
+                                          R &as, R &an)
 {
     const bool edge = i == 0 || j == 0 || i == L.nx - 1 || j == L.ny - 1;
     if (!VARK && !edge) {
-        ap = make_double2(c.apr, c.api);
-        winv = make_double2(c.wr, c.wi);
-        aw = ae = -L.ihx2;
-        as = an = -L.ihy2;
+        ap = mkc<R>(c.apr, c.api);
+        winv = mkc<R>(c.wr, c.wi);
+        aw = ae = c.ax;
+        as = an = c.ay;
         return true;
     }
-    if (!coef5(L, s, i, j, ap, aw, ae, as, an)) return false;
-    winv = cscal(omega, cinv(ap));
+    if constexpr (std::is_same<R, double>::value) {
+        if (!coef5(L, s, i, j, ap, aw, ae, as, an)) return false;
+        winv = cscal(omega, cinv(ap));
+    } else {
+        cd apd;
+        double awd, aed, asd, and_;
+        if (!coef5(L, s, i, j, apd, awd, aed, asd, and_)) return false;
+        ap = cvt<R>(apd);
+        winv = cvt<R>(cscal(omega, cinv(apd)));
+        aw = (R)awd;
+        ae = (R)aed;
+        as = (R)asd;
+        an = (R)and_;
+    }
     return true;
 }
 
@@ -205,27 +252,31 @@ __device__ __forceinline__ bool node_coef(const Lev &L, cd s, double omega, cons
 //   rc = full weighting of r1      (1/16 [1 2 1; 2 4 2; 1 2 1], truncated)
 // One block computes a 32 x 8 tile of coarse nodes from the 67 x 19 fine
 // region it needs: r and x1 live in LDS, r1 overwrites r in place.
+// Types: r is read in precision RI, everything is computed and rc stored in
+// precision R (RI = R = double for the FP64 cycle; RI = double, R = float on
+// the top level of the mixed-precision cycle; float, float below it).
 // ------------------------------------------------------------------------
 constexpr int VD_CX = 32, VD_CY = 8;
 constexpr int VD_X1W = 2 * VD_CX + 3, VD_X1H = 2 * VD_CY + 3;  // 67 x 19
 
-template <bool VARK>
-__global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double omega, Smooth c,
-                                                 const cd *__restrict__ r,
-                                                 const cd *__restrict__ rs, cd *__restrict__ rc,
-                                                 int tiles_x)
+template <bool VARK, class RI, class R>
+__global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double omega,
+                                                 Smooth<R> c, const cx<RI> *__restrict__ r,
+                                                 const cd *__restrict__ rs,
+                                                 cx<R> *__restrict__ rc, int tiles_x)
 {
     // Thread (cx, cy) computes coarse node (I0+cx, J0+cy) and owns the 2 x 2
     // fine nodes (2I+dx, 2J+dy), keeping r and then r1 there in registers.
     // One LDS tile (67 x 19, local (a, b) = fine (2*I0-2+a, 2*J0-2+b)) holds
     // x1, then is reused for r1.  The 249 halo nodes of the tile are spread
     // one per thread; those on the r1 ring (a == 1 or b == 1) also get r1.
-    const double rsc = rs ? rs[0].x : 1.0;  // right-hand side = rsc * r
-    __shared__ cd st[VD_X1H][VD_X1W];
+    typedef cx<R> C;
+    const R rsc = rs ? (R)rs[0].x : (R)1;  // right-hand side = rsc * r
+    __shared__ C st[VD_X1H][VD_X1W];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int I0 = (t % tiles_x) * VD_CX, J0 = (t / tiles_x) * VD_CY;
     const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
-    const int cx = threadIdx.x % VD_CX, cy = threadIdx.x / VD_CX;
+    const int cx_ = threadIdx.x % VD_CX, cy = threadIdx.x / VD_CX;
     // halo node of this thread
     int ha = -1, hb = -1;
     {
@@ -240,88 +291,107 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
             ha = 2 + qq % (2 * VD_CX);
         }
     }
-    // ---- global loads (unconditional, from a valid address)
-    cd rown[4], rhalo;
+    // ---- global loads (unconditional, from a valid address); r is taken
+    // as 0 at non-unknown nodes (Dirichlet boundary) and outside the grid
+    C rown[4], rhalo;
 #pragma unroll
     for (int d = 0; d < 4; d++) {
-        const int fi = fi0 + 2 + 2 * cx + (d & 1), fj = fj0 + 2 + 2 * cy + (d >> 1);
-        const bool in = fi < Lf.nx && fj < Lf.ny;
-        const cd v = r[in ? (size_t)fj * Lf.nx + fi : 0];
-        rown[d] = in ? (rs ? cscal(rsc, v) : v) : czero();
+        const int fi = fi0 + 2 + 2 * cx_ + (d & 1), fj = fj0 + 2 + 2 * cy + (d >> 1);
+        const bool in = fi < Lf.nx && fj < Lf.ny && unknown(Lf, fi, fj);
+        const C v = cvt<R>(r[in ? (size_t)fj * Lf.nx + fi : 0]);
+        rown[d] = in ? (rs ? cscal(rsc, v) : v) : zc<R>();
     }
     {
         const int fi = fi0 + ha, fj = fj0 + hb;
-        const bool in = ha >= 0 && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny;
-        const cd v = r[in ? (size_t)fj * Lf.nx + fi : 0];
-        rhalo = in ? (rs ? cscal(rsc, v) : v) : czero();
+        const bool in = ha >= 0 && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny &&
+                        unknown(Lf, fi, fj);
+        const C v = cvt<R>(r[in ? (size_t)fj * Lf.nx + fi : 0]);
+        rhalo = in ? (rs ? cscal(rsc, v) : v) : zc<R>();
     }
-    // r at non-unknown nodes (Dirichlet boundary) and outside the grid is 0
-    auto x1_at = [&](int fi, int fj, cd &rv) -> cd {
-        cd ap, wv;
-        double aw, ae, as, an;
+    auto x1_at = [&](int fi, int fj, C rv) -> C {
+        C ap, wv;
+        R aw, ae, as, an;
         if (fi < 0 || fi >= Lf.nx || fj < 0 || fj >= Lf.ny ||
-            !node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an)) {
-            rv = czero();
-            return czero();
-        }
+            !node_coef<VARK, R>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
+            return zc<R>();
         return cmul(wv, rv);
     };
 #pragma unroll
     for (int d = 0; d < 4; d++)
-        st[2 + 2 * cy + (d >> 1)][2 + 2 * cx + (d & 1)] =
-            x1_at(fi0 + 2 + 2 * cx + (d & 1), fj0 + 2 + 2 * cy + (d >> 1), rown[d]);
+        st[2 + 2 * cy + (d >> 1)][2 + 2 * cx_ + (d & 1)] =
+            x1_at(fi0 + 2 + 2 * cx_ + (d & 1), fj0 + 2 + 2 * cy + (d >> 1), rown[d]);
     if (ha >= 0) st[hb][ha] = x1_at(fi0 + ha, fj0 + hb, rhalo);
     __syncthreads();
     // ---- r1 = r - M x1 at the owned nodes and the r1 ring
-    auto r1_at = [&](int a, int b, cd rv) -> cd {
+    auto r1_at = [&](int a, int b, C rv) -> C {
         const int fi = fi0 + a, fj = fj0 + b;
-        cd ap, wv;
-        double aw, ae, as, an;
+        C ap, wv;
+        R aw, ae, as, an;
         if (fi < 0 || fi >= Lf.nx || fj < 0 || fj >= Lf.ny ||
-            !node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
-            return czero();
-        cd m = cmul(ap, st[b][a]);
+            !node_coef<VARK, R>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
+            return zc<R>();
+        C m = cmul(ap, st[b][a]);
         caxpy(m, aw, st[b][a - 1]);
         caxpy(m, ae, st[b][a + 1]);
         caxpy(m, as, st[b - 1][a]);
         caxpy(m, an, st[b + 1][a]);
         return csub(rv, m);
     };
-    cd r1own[4], r1halo = czero();
+    C r1own[4], r1halo = zc<R>();
 #pragma unroll
-    for (int d = 0; d < 4; d++) r1own[d] = r1_at(2 + 2 * cx + (d & 1), 2 + 2 * cy + (d >> 1), rown[d]);
+    for (int d = 0; d < 4; d++)
+        r1own[d] = r1_at(2 + 2 * cx_ + (d & 1), 2 + 2 * cy + (d >> 1), rown[d]);
     const bool ring = ha >= 1 && ha <= VD_X1W - 2 && hb >= 1 && hb <= VD_X1H - 2;
     if (ring) r1halo = r1_at(ha, hb, rhalo);
     __syncthreads();
 #pragma unroll
-    for (int d = 0; d < 4; d++) st[2 + 2 * cy + (d >> 1)][2 + 2 * cx + (d & 1)] = r1own[d];
+    for (int d = 0; d < 4; d++) st[2 + 2 * cy + (d >> 1)][2 + 2 * cx_ + (d & 1)] = r1own[d];
     if (ring) st[hb][ha] = r1halo;
     __syncthreads();
     // ---- full weighting around fine node (2I, 2J) = local (2cx+2, 2cy+2)
-    const int I = I0 + cx, J = J0 + cy;
+    const int I = I0 + cx_, J = J0 + cy;
     if (I >= Lc.nx || J >= Lc.ny) return;
-    cd v = czero();
+    C v = zc<R>();
     if (unknown(Lc, I, J)) {
-        const int a = 2 * cx + 2, bb = 2 * cy + 2;
-        cd ce = cscal(4.0, st[bb][a]);
-        cd e = cadd(cadd(st[bb][a - 1], st[bb][a + 1]), cadd(st[bb - 1][a], st[bb + 1][a]));
-        cd d = cadd(cadd(st[bb - 1][a - 1], st[bb - 1][a + 1]),
-                    cadd(st[bb + 1][a - 1], st[bb + 1][a + 1]));
-        v = cscal(1.0 / 16.0, cadd(cadd(ce, cscal(2.0, e)), d));
+        const int a = 2 * cx_ + 2, bb = 2 * cy + 2;
+        C ce = cscal((R)4, st[bb][a]);
+        C e = cadd(cadd(st[bb][a - 1], st[bb][a + 1]), cadd(st[bb - 1][a], st[bb + 1][a]));
+        C d = cadd(cadd(st[bb - 1][a - 1], st[bb - 1][a + 1]),
+                   cadd(st[bb + 1][a - 1], st[bb + 1][a + 1]));
+        v = cscal((R)(1.0 / 16.0), cadd(cadd(ce, cscal((R)2, e)), d));
     }
     rc[(size_t)J * Lc.nx + I] = v;
+}
+
+template <class RI, class R>
+static hipError_t vc_down_t(const Lev &Lf, const Lev &Lc, cd s, double omega, const cx<RI> *r,
+                            const cd *rs, cx<R> *rc, hipStream_t st)
+{
+    const int tx = cdiv(Lc.nx, VD_CX), ty = cdiv(Lc.ny, VD_CY);
+    const Smooth<R> c = smooth_consts<R>(Lf, s, omega);
+    if (Lf.k)
+        k_vc_down<true, RI, R><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx);
+    else
+        k_vc_down<false, RI, R><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx);
+    HD_LAUNCH_CHECK();
 }
 
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
                           const cd *rs, cd *rc, hipStream_t st)
 {
-    const int tx = cdiv(Lc.nx, VD_CX), ty = cdiv(Lc.ny, VD_CY);
-    const Smooth c = smooth_consts(Lf, s, omega);
-    if (Lf.k)
-        k_vc_down<true><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx);
-    else
-        k_vc_down<false><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx);
-    HD_LAUNCH_CHECK();
+    return vc_down_t<double, double>(Lf, Lc, s, omega, r, rs, rc, st);
+}
+
+hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r, cf *rc,
+                          hipStream_t st)
+{
+    return vc_down_t<double, float>(Lf, Lc, s, omega, r, nullptr, rc, st);
+}
+
+hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r, cf *rc,
+                          hipStream_t st)
+{
+    return vc_down_t<float, float>(Lf, Lc, s, omega, r, nullptr, rc, st);
 }
 
 // ------------------------------------------------------------------------
@@ -332,25 +402,29 @@ hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, cons
 //   out = x3 [+ Z v2] [+ out]
 // One block writes a 64 x 16 fine tile.  r (66 x 18), the coarse correction
 // tile (34 x 10) and x2 (66 x 18) live in LDS.
+// Types: r is read in precision RI, ec and the arithmetic are in R, out is
+// stored in RO; Z v2 (always FP64, level-0 deflation term) is added in FP64
+// when RO is double.
 // ------------------------------------------------------------------------
 constexpr int VU_TX = 64, VU_TY = 16;
 constexpr int VU_W = VU_TX + 2, VU_H = VU_TY + 2;
 constexpr int VU_CW = VU_TX / 2 + 2, VU_CH = VU_TY / 2 + 2;  // 34 x 10
 
-template <bool VARK>
-__global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omega, Smooth c,
-                                               const cd *__restrict__ r,
+template <bool VARK, class RI, class R, class RO>
+__global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omega, Smooth<R> c,
+                                               const cx<RI> *__restrict__ r,
                                                const cd *__restrict__ rs,
-                                               const cd *__restrict__ ec, cd *__restrict__ out,
-                                               int accumulate, const cd *__restrict__ v2,
-                                               int zho, int tiles_x)
+                                               const cx<R> *__restrict__ ec,
+                                               cx<RO> *__restrict__ out, int accumulate,
+                                               const cd *__restrict__ v2, int zho, int tiles_x)
 {
     // Thread (tx, ty) owns output column tx and rows 4*ty .. 4*ty+3 of the
     // 64 x 16 tile and keeps r there in registers; x2 (66 x 18 with its
     // one-node halo) and the coarse correction tile (34 x 10) live in LDS.
-    const double rsc = rs ? rs[0].x : 1.0;  // right-hand side = rsc * r
-    __shared__ cd sx2[VU_H][VU_W];
-    __shared__ cd se[VU_CH][VU_CW];
+    typedef cx<R> C;
+    const R rsc = rs ? (R)rs[0].x : (R)1;  // right-hand side = rsc * r
+    __shared__ C sx2[VU_H][VU_W];
+    __shared__ C se[VU_CH][VU_CW];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i0 = (t % tiles_x) * VU_TX, j0 = (t / tiles_x) * VU_TY;
     const int ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // coarse tile origin
@@ -376,29 +450,29 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
         }
     }
     // ---- all global loads first (unconditional, from a valid address)
-    cd el[NKC], rown[4], rhalo;
+    C el[NKC], rown[4], rhalo;
 #pragma unroll
     for (int kq = 0; kq < NKC; kq++) {
         const int q = threadIdx.x + 256 * kq;
         const int I = ci0 + q % VU_CW, J = cj0 + q / VU_CW;
         const bool in = q < NC && I >= 0 && I < Lc.nx && J >= 0 && J < Lc.ny && unknown(Lc, I, J);
-        const cd v = ec[in ? (size_t)J * Lc.nx + I : 0];
-        el[kq] = in ? v : czero();
+        const C v = ec[in ? (size_t)J * Lc.nx + I : 0];
+        el[kq] = in ? v : zc<R>();
     }
     const int i = i0 + tx;
 #pragma unroll
     for (int rr = 0; rr < 4; rr++) {
         const int j = j0 + 4 * ty + rr;
         const bool in = i < Lf.nx && j < Lf.ny && unknown(Lf, i, j);
-        const cd v = r[in ? (size_t)j * Lf.nx + i : 0];
-        rown[rr] = in ? (rs ? cscal(rsc, v) : v) : czero();
+        const C v = cvt<R>(r[in ? (size_t)j * Lf.nx + i : 0]);
+        rown[rr] = in ? (rs ? cscal(rsc, v) : v) : zc<R>();
     }
     {
         const int fi = i0 - 1 + ha, fj = j0 - 1 + hb;
         const bool in = ha >= 0 && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny &&
                         unknown(Lf, fi, fj);
-        const cd v = r[in ? (size_t)fj * Lf.nx + fi : 0];
-        rhalo = in ? (rs ? cscal(rsc, v) : v) : czero();
+        const C v = cvt<R>(r[in ? (size_t)fj * Lf.nx + fi : 0]);
+        rhalo = in ? (rs ? cscal(rsc, v) : v) : zc<R>();
     }
 #pragma unroll
     for (int kq = 0; kq < NKC; kq++) {
@@ -407,21 +481,21 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
     }
     __syncthreads();
     // ---- x2 = omega D^-1 r + P ec at the owned nodes and the halo node
-    auto x2_at = [&](int fi, int fj, cd rv) -> cd {
-        cd ap, wv;
-        double aw, ae, as, an;
+    auto x2_at = [&](int fi, int fj, C rv) -> C {
+        C ap, wv;
+        R aw, ae, as, an;
         if (fi < 0 || fi >= Lf.nx || fj < 0 || fj >= Lf.ny ||
-            !node_coef<VARK>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
-            return czero();
+            !node_coef<VARK, R>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
+            return zc<R>();
         // bilinear interpolation from the coarse tile: coarse node
         // (fi >> 1, fj >> 1) sits at se[(fj >> 1) - cj0][(fi >> 1) - ci0]
         const int ca = (fi >> 1) - ci0, cb = (fj >> 1) - cj0;
-        cd p = se[cb][ca];
-        if (fi & 1) p = cscal(0.5, cadd(p, se[cb][ca + 1]));
+        C p = se[cb][ca];
+        if (fi & 1) p = cscal((R)0.5, cadd(p, se[cb][ca + 1]));
         if (fj & 1) {
-            cd p2 = se[cb + 1][ca];
-            if (fi & 1) p2 = cscal(0.5, cadd(p2, se[cb + 1][ca + 1]));
-            p = cscal(0.5, cadd(p, p2));
+            C p2 = se[cb + 1][ca];
+            if (fi & 1) p2 = cscal((R)0.5, cadd(p2, se[cb + 1][ca + 1]));
+            p = cscal((R)0.5, cadd(p, p2));
         }
         return cadd(cmul(wv, rv), p);
     };
@@ -441,60 +515,90 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
         if (j >= Lf.ny) break;
         const int a = tx + 1, bb = jl + 1;
         const size_t p = (size_t)j * Lf.nx + i;
-        cd ap, wv;
-        double aw, ae, as, an;
-        cd v = czero();
-        if (node_coef<VARK>(Lf, s, omega, c, i, j, ap, wv, aw, ae, as, an)) {
-            cd m = cmul(ap, sx2[bb][a]);
+        C ap, wv;
+        R aw, ae, as, an;
+        cx<RO> v = zc<RO>();
+        if (node_coef<VARK, R>(Lf, s, omega, c, i, j, ap, wv, aw, ae, as, an)) {
+            C m = cmul(ap, sx2[bb][a]);
             caxpy(m, aw, sx2[bb][a - 1]);
             caxpy(m, ae, sx2[bb][a + 1]);
             caxpy(m, as, sx2[bb - 1][a]);
             caxpy(m, an, sx2[bb + 1][a]);
-            v = cadd(sx2[bb][a], cmul(wv, csub(rown[rr], m)));
-            if (v2) v = cadd(v, prolong_at(Lc, v2, i, j, zho));
+            v = cvt<RO>(cadd(sx2[bb][a], cmul(wv, csub(rown[rr], m))));
+            if (v2) v = cadd(v, cvt<RO>(prolong_at(Lc, v2, i, j, zho)));
         }
         if (accumulate) v = cadd(v, out[p]);
         out[p] = v;
     }
 }
 
+template <class RI, class R, class RO>
+static hipError_t vc_up_t(const Lev &Lf, const Lev &Lc, cd s, double omega, const cx<RI> *r,
+                          const cd *rs, const cx<R> *ec, cx<RO> *out, int accumulate,
+                          const cd *v2, int zho, hipStream_t st)
+{
+    const int tx = cdiv(Lf.nx, VU_TX), ty = cdiv(Lf.ny, VU_TY);
+    const Smooth<R> c = smooth_consts<R>(Lf, s, omega);
+    if (Lf.k)
+        k_vc_up<true, RI, R, RO><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out,
+                                                          accumulate, v2, zho, tx);
+    else
+        k_vc_up<false, RI, R, RO><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out,
+                                                           accumulate, v2, zho, tx);
+    HD_LAUNCH_CHECK();
+}
+
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
                         const cd *rs, const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
                         hipStream_t st)
 {
-    const int tx = cdiv(Lf.nx, VU_TX), ty = cdiv(Lf.ny, VU_TY);
-    const Smooth c = smooth_consts(Lf, s, omega);
-    if (Lf.k)
-        k_vc_up<true><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out, accumulate, v2,
-                                               zho, tx);
-    else
-        k_vc_up<false><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out, accumulate, v2,
-                                                zho, tx);
-    HD_LAUNCH_CHECK();
+    return vc_up_t<double, double, double>(Lf, Lc, s, omega, r, rs, ec, out, accumulate, v2, zho,
+                                           st);
+}
+
+hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
+                        const cf *ec, cd *out, int accumulate, const cd *v2, int zho,
+                        hipStream_t st)
+{
+    return vc_up_t<double, float, double>(Lf, Lc, s, omega, r, nullptr, ec, out, accumulate, v2,
+                                          zho, st);
+}
+
+hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
+                        const cf *ec, cf *out, hipStream_t st)
+{
+    return vc_up_t<float, float, float>(Lf, Lc, s, omega, r, nullptr, ec, out, 0, nullptr, 0, st);
 }
 
 // ------------------------------------------------------------------------
-// Coarsest level: x = Minv r with the precomputed dense inverse.  One wave per
-// row: the lanes stride along the row (coalesced) and reduce by shuffles.
+// Coarsest level: x = Minv r with the precomputed dense inverse (FP64, or its
+// FP32 rounding for the mixed-precision cycle).  One wave per row: the lanes
+// stride along the row (coalesced) and reduce by shuffles.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ cd wave_sum64(cd v)
+__device__ __forceinline__ double shfl_xor64(double v, int o) { return __shfl_xor(v, o, 64); }
+__device__ __forceinline__ float shfl_xor64(float v, int o) { return __shfl_xor(v, o, 64); }
+
+template <class R>
+__device__ __forceinline__ cx<R> wave_sum64(cx<R> v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        v.x += __shfl_xor(v.x, o, 64);
-        v.y += __shfl_xor(v.y, o, 64);
+        v.x += shfl_xor64(v.x, o);
+        v.y += shfl_xor64(v.y, o);
     }
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_coarsest(int n, const cd *__restrict__ Minv,
-                                                  const cd *__restrict__ r, cd *__restrict__ x)
+template <class R>
+__global__ __launch_bounds__(256) void k_coarsest(int n, const cx<R> *__restrict__ Minv,
+                                                  const cx<R> *__restrict__ r,
+                                                  cx<R> *__restrict__ x)
 {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
-    cd s0 = czero(), s1 = czero(), s2 = czero(), s3 = czero();
-    const cd *m = Minv + (size_t)row * n;
+    cx<R> s0 = zc<R>(), s1 = zc<R>(), s2 = zc<R>(), s3 = zc<R>();
+    const cx<R> *m = Minv + (size_t)row * n;
     int c = lane;
     for (; c + 192 < n; c += 256) {
         s0 = cadd(s0, cmul(m[c], r[c]));
@@ -503,13 +607,19 @@ __global__ __launch_bounds__(256) void k_coarsest(int n, const cd *__restrict__ 
         s3 = cadd(s3, cmul(m[c + 192], r[c + 192]));
     }
     for (; c < n; c += 64) s0 = cadd(s0, cmul(m[c], r[c]));
-    cd s = wave_sum64(cadd(cadd(s0, s1), cadd(s2, s3)));
+    cx<R> s = wave_sum64<R>(cadd(cadd(s0, s1), cadd(s2, s3)));
     if (lane == 0) x[row] = s;
 }
 
 hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st)
 {
-    k_coarsest<<<cdiv(n, 4), 256, 0, st>>>(n, Minv, r, x);
+    k_coarsest<double><<<cdiv(n, 4), 256, 0, st>>>(n, Minv, r, x);
+    HD_LAUNCH_CHECK();
+}
+
+hipError_t launch_coarsest(int n, const cf *Minv, const cf *r, cf *x, hipStream_t st)
+{
+    k_coarsest<float><<<cdiv(n, 4), 256, 0, st>>>(n, Minv, r, x);
     HD_LAUNCH_CHECK();
 }
 

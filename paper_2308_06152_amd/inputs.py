@@ -39,12 +39,24 @@ class Workload:
     coarse_restart: int = 30
     coarse_tol: float = 1e-1
     coarse_maxit: int = 300
+    model: str = "const"     # "const" (k = kconst) or "wedge" (k from the velocity model)
+    freq: float = 0.0        # frequency in Hz for a velocity model
 
     @property
     def npts(self) -> int:
         return self.nx * self.ny
 
+    def kfield(self):
+        """The wavenumber field [ny][nx] (None for a constant k)."""
+        if self.model == "wedge":
+            return 2.0 * math.pi * self.freq / wedge_velocity(self.nx, self.ny, self.hx, self.hy)
+        return None
+
     def rhs(self) -> np.ndarray:
+        if self.model == "wedge":
+            # source at (300 m, 0 m): the middle of the top edge
+            return point_source(self.nx, self.ny, self.hx, self.hy, (self.nx - 1) // 2,
+                                self.ny - 1)
         ic, jc = (self.nx - 1) // 2, (self.ny - 1) // 2
         if self.source == "point":
             return point_source(self.nx, self.ny, self.hx, self.hy, ic, jc)
@@ -129,3 +141,39 @@ def scaled_plain(n: int, k: float, bc: int = BC_SOMMERFELD,
     nx, ny, hx, hy = unit_square(n)
     return Workload(f"unit_{n}_k{k:g}_bc{bc}_c{coarse_op}", nx, ny, hx, hy, bc, k, source,
                     coarse_op)
+
+
+# The wedge model (the paper's layered test, Section 2): x in [0, 600] m,
+# y in [-1000, 0] m (node row j = 0 at the bottom), three layers of 2000, 1500
+# and 3000 m/s from the top down, split by two sloping planar interfaces.  The
+# paper's figure of the geometry is not available; the interfaces used here are
+#   upper: y = -400 + 100 * x / 600   (from -400 m at x = 0 to -300 m at 600)
+#   lower: y = -750 + 250 * x / 600   (from -750 m to -500 m; they never meet).
+WEDGE_X, WEDGE_Y = 600.0, 1000.0
+WEDGE_C = (2000.0, 1500.0, 3000.0)
+
+
+def wedge_interfaces(x):
+    return -400.0 + 100.0 * x / WEDGE_X, -750.0 + 250.0 * x / WEDGE_X
+
+
+def wedge_velocity(nx: int, ny: int, hx: float, hy: float) -> np.ndarray:
+    x = np.arange(nx) * hx
+    y = -WEDGE_Y + np.arange(ny) * hy
+    up, lo = wedge_interfaces(x)
+    Y = y[:, None]
+    return np.where(Y >= up[None, :], WEDGE_C[0],
+                    np.where(Y >= lo[None, :], WEDGE_C[1], WEDGE_C[2])).astype(np.float64)
+
+
+def wedge(nx: int = 1153, ny: int = 1921, freq: float | None = None) -> Workload:
+    """The wedge on an nx x ny grid (h = 600/(nx-1) = 1000/(ny-1) for the
+    paper's 9*2^q+1 x 15*2^q+1 grids).  The frequency defaults to 40 Hz on the
+    1153 x 1921 grid and scales with 1/h below it (same points per wavelength,
+    kh <= 0.087).  Sommerfeld boundary, point source at the top centre,
+    Galerkin (str-Glk) coarse operator, coarse GMRES(30) to 0.1."""
+    hx, hy = WEDGE_X / (nx - 1), WEDGE_Y / (ny - 1)
+    if freq is None:
+        freq = 40.0 * (nx - 1) / 1152.0
+    return Workload(f"wedge_{nx}x{ny}_f{freq:g}", nx, ny, hx, hy, BC_SOMMERFELD, 0.0, "point",
+                    COARSE_GALERKIN, model="wedge", freq=freq)

@@ -47,6 +47,7 @@ def test_defaults_and_strerror(H):
     assert (o.restart, o.tol, o.coarse_tol, o.coarse_restart) == (50, 1e-6, 0.1, 30)
     assert o.defl_vectors == H.Z_HIGH
     assert o.coarsest_nodes == 1089
+    assert o.precision == H.PREC_FP64
     L = H.load()
     assert L.helm_strerror(0) == b"success"
     assert b"coarsen" in L.helm_strerror(H.HELM_EGRID)
@@ -71,7 +72,8 @@ def test_create_rejects_uncoarsenable_grids(H, nx, ny):
                                 dict(restart=61), dict(coarse_restart=0), dict(coarse_iters=0),
                                 dict(coarse_mode=0), dict(coarse_op=7), dict(defl_vectors=3),
                                 dict(omega=0.0), dict(tol=-1.0), dict(coarsest_nodes=-1),
-                                dict(coarsest_nodes=5000)])
+                                dict(coarsest_nodes=5000), dict(precision=2),
+                                dict(precision=-1)])
 def test_create_rejects_bad_options(H, kw):
     assert _create(H, 9, 9, **kw) == H.HELM_EINVAL
 

@@ -1,0 +1,114 @@
+"""Mixed-precision V-cycle (complex64 arithmetic on every level, FP64 input and
+output) against the FP64 oracle.
+
+Bar for the cycle and for A-DEF1 with a fixed inner count: <= 1e-5 relative,
+against the oracle applied to the FP32-rounded input (so the input rounding is
+not counted).  Whole solves: FGMRES absorbs the perturbed preconditioner, so
+the FP64 true residual must still reach 1e-6 and the outer iteration count stay
+within one of the FP64 oracle's.
+"""
+import numpy as np
+import pytest
+
+from paper_2308_06152_amd import inputs
+
+from test_gpu_parity import CASES, H, dev, host, make_pair, rel  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MIXED = 1
+
+
+def r32(a):
+    """Round a complex128 array to complex64 and back."""
+    return a.astype(np.complex64).astype(np.complex128)
+
+
+@pytest.mark.parametrize("coarsest", [0, 1089])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_mixed_vcycle_parity(H, ora, case, coarsest):
+    S, P = make_pair(H, ora, case, coarsest_nodes=coarsest, precision=MIXED)
+    assert S.opts.precision == MIXED
+    r = r32(inputs.random_complex((P.ny, P.nx), 131))
+    got = host(S.vcycle(dev(r)))
+    want = ora.vcycle(P, r)
+    assert rel(got, want) <= 1e-5
+    # and it is not the FP64 cycle
+    S64, _ = make_pair(H, ora, case, coarsest_nodes=coarsest)
+    got64 = host(S64.vcycle(dev(r)))
+    assert rel(got64, want) <= 1e-12
+    if P.nx * P.ny > 100:
+        assert rel(got, want) > 1e-12
+
+
+def test_mixed_vcycle_large_wavenumber(H, ora):
+    """k h = 0.2 on 513^2 (the 4097^2, k = 800 workload's kh), Sommerfeld."""
+    case = ("som513_k100", 513, 513, 1, "const", 100.0, 1)
+    S, P = make_pair(H, ora, case, precision=MIXED)
+    r = r32(inputs.random_complex((P.ny, P.nx), 132))
+    assert rel(host(S.vcycle(dev(r))), ora.vcycle(P, r)) <= 1e-5
+
+
+@pytest.mark.parametrize("case", CASES[:6], ids=[c[0] for c in CASES[:6]])
+def test_mixed_deflate_apply_parity(H, ora, case):
+    n_it = 8
+    S, P = make_pair(H, ora, case, coarse_mode=1, coarse_iters=n_it, coarse_restart=30,
+                     precision=MIXED)
+    Po = P.replace(coarse_mode=ora.CMODE_FIXED, coarse_iters=n_it, coarse_restart=30)
+    v = r32(inputs.random_complex((P.ny, P.nx), 133))
+    got = host(S.deflate(dev(v), 2))
+    want, _ = ora.deflate_apply(Po, v, 2)
+    assert rel(got, want) <= 1e-5
+    # the Q and P parts do not involve the fine-grid cycle: still FP64-exact
+    assert rel(host(S.deflate(dev(v), 1)), ora.deflate_apply(Po, v, 1)[0]) <= 1e-11
+
+
+def _wedge_pair(H, ora, w, **kw):
+    kf = w.kfield()
+    okw = dict(coarse_op=w.coarse_op, coarse_mode=2, coarse_tol=w.coarse_tol,
+               coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart, restart=w.restart,
+               tol=w.tol)
+    okw.update(kw)
+    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, k=dev(kf), **okw)
+    P = ora.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, k=kf, coarse_op=w.coarse_op,
+                    coarsest_nodes=S.opts.coarsest_nodes,
+                    coarse_mode=ora.CMODE_TOL if okw["coarse_mode"] == 2 else ora.CMODE_FIXED,
+                    coarse_tol=okw["coarse_tol"], coarse_iters=okw["coarse_iters"],
+                    coarse_restart=okw["coarse_restart"])
+    return S, P
+
+
+def test_mixed_solve_wedge(H, ora):
+    """The wedge model (variable k, Galerkin coarse operator) on 145 x 241:
+    the mixed-precision solve converges to the FP64 tolerance within one outer
+    iteration of the FP64 oracle, and its solution matches the oracle's to the
+    accuracy the tolerance allows."""
+    w = inputs.wedge(145, 241)
+    S, P = _wedge_pair(H, ora, w, precision=MIXED)
+    b = w.rhs()
+    x, info = S.solve(dev(b))
+    info = info[0]
+    xo, io = ora.fgmres(P, b, restart=w.restart, tol=w.tol, maxit=200)
+    assert info["converged"] and io.converged
+    assert abs(info["outer_iters"] - io.iters) <= 1
+    xg = host(x)
+    r = ora.helm_apply(P, xg) - b
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
+    # both are 1e-6-residual solutions: their difference is bounded by the
+    # conditioning, here well inside 1e-4
+    assert rel(xg, xo) <= 1e-4
+
+
+def test_mixed_solve_equal_iterations(H, ora):
+    """At a forced equal outer count with a fixed inner count, the mixed and the
+    FP64 oracle iterates agree to the FP32 level."""
+    w = inputs.wedge(73, 121)
+    S, P = _wedge_pair(H, ora, w, precision=MIXED, coarse_mode=1, coarse_iters=10,
+                       force_iters=6)
+    Po = P.replace(coarse_mode=ora.CMODE_FIXED, coarse_iters=10)
+    b = w.rhs()
+    x, info = S.solve(dev(b))
+    xo, io = ora.fgmres(Po, b, restart=w.restart, tol=w.tol, maxit=200, force_iters=6)
+    assert info[0]["outer_iters"] == io.iters == 6
+    assert rel(host(x), xo) <= 1e-5

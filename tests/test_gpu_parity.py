@@ -79,7 +79,8 @@ def make_pair(H, ora, case, coarsest_nodes=1089, **kw):
     gkw = {k2: v for k2, v in okw.items() if k2 in ("coarse_op", "defl_vectors", "coarse_restart",
                                                       "coarse_tol", "beta_re", "beta_im", "omega",
                                                       "coarse_mode", "coarse_iters", "restart",
-                                                      "tol", "maxit", "force_iters")}
+                                                      "tol", "maxit", "force_iters",
+                                                      "precision")}
     kt = dev(kfield) if kfield is not None else None
     S = H.Solver(nx, ny, h, h, bc, k=kt, kconst=kconst, coarsest_nodes=coarsest_nodes, **gkw)
     return S, P
