@@ -112,3 +112,27 @@ def test_mixed_solve_equal_iterations(H, ora):
     xo, io = ora.fgmres(Po, b, restart=w.restart, tol=w.tol, maxit=200, force_iters=6)
     assert info[0]["outer_iters"] == io.iters == 6
     assert rel(host(x), xo) <= 1e-5
+
+
+def test_mixed_wedge_full_size(H, ora):
+    """The 1153 x 1921 wedge at 40 Hz: the mixed-precision and FP64 solves both
+    reach the FP64 tolerance (true residual recomputed by the oracle operator)
+    with the same outer count to within one, and their solutions agree to the
+    level two 1e-6-residual solutions can."""
+    w = inputs.wedge()
+    sols = {}
+    for prec in (0, MIXED):
+        S, P = _wedge_pair(H, ora, w, precision=prec)
+        b = w.rhs()
+        x, info = S.solve(dev(b))
+        xg = host(x)
+        r = ora.helm_apply(P, xg) - b
+        relres = np.linalg.norm(r) / np.linalg.norm(b)
+        assert info[0]["converged"] and relres <= 1e-6, (prec, info, relres)
+        sols[prec] = (xg, info[0]["outer_iters"])
+        print(f"wedge 1153x1921 precision={prec}: outer {info[0]['outer_iters']}, "
+              f"inner {info[0]['inner_iters_total']}, relres {relres:.3e}")
+    assert abs(sols[0][1] - sols[MIXED][1]) <= 1
+    d = rel(sols[MIXED][0], sols[0][0])
+    print(f"wedge 1153x1921: ||x_mixed - x_fp64|| / ||x_fp64|| = {d:.3e}")
+    assert d <= 1e-4
