@@ -22,7 +22,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 BC_DIRICHLET, BC_SOMMERFELD = 0, 1
 Z_LINEAR, Z_HIGH = 0, 1
-COARSE_GALERKIN, COARSE_REDGLK2 = 0, 1
+COARSE_GALERKIN, COARSE_REDGLK2, COARSE_REDO2, COARSE_REDO4, COARSE_REDGLK1 = 0, 1, 2, 3, 4
 CMODE_EXACT, CMODE_FIXED, CMODE_TOL = 0, 1, 2
 DEFL_Q, DEFL_P, DEFL_ADEF1 = 0, 1, 2
 PRECOND_VCYCLE, PRECOND_EXACT_A = 0, 1
@@ -131,6 +131,8 @@ def lib() -> ctypes.CDLL:
                                  ctypes.c_int, ctypes.POINTER(_Info)]
         L.ora_gmres_left.argtypes = [P, D, D, ctypes.c_double, ctypes.c_int,
                                      ctypes.POINTER(_Info)]
+        L.ora_gcr.argtypes = [P, D, D, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                              ctypes.c_int, ctypes.POINTER(_Info)]
         _lib = L
     return _lib
 
@@ -275,6 +277,20 @@ def fgmres(p: Problem, b, restart: int = 50, tol: float = 1e-6, maxit: int = 500
     inf = _Info()
     _check(lib().ora_fgmres(ctypes.byref(c), _ptr(b), _ptr(x), restart, tol, maxit,
                             force_iters, ctypes.byref(inf)), "fgmres")
+    del keep
+    return x, Info(inf.iters, bool(inf.converged), inf.inner_total, inf.inner_max, inf.relres)
+
+
+def gcr(p: Problem, b, restart: int = 50, tol: float = 1e-6, maxit: int = 500,
+        force_iters: int = 0):
+    """(x, Info): right-preconditioned GCR(restart) with P_A-DEF1."""
+    s = (p.ny, p.nx)
+    c, keep = p._c()
+    b = _cin(b, s)
+    x = np.empty(s, np.complex128)
+    inf = _Info()
+    _check(lib().ora_gcr(ctypes.byref(c), _ptr(b), _ptr(x), restart, tol, maxit, force_iters,
+                         ctypes.byref(inf)), "gcr")
     del keep
     return x, Info(inf.iters, bool(inf.converged), inf.inner_total, inf.inner_max, inf.relres)
 

@@ -683,12 +683,112 @@ static void coarse_redglk2(const hier_t *H, const cplx *u, cplx *y)
         }
 }
 
+/* One row of the second-order 5-point Helmholtz stencil at the coarse
+ * spacing (Section 2.1, with its Sommerfeld closure) applied to u at (I, J):
+ * the rows of ReD-O2 and the near-boundary rows of ReD-O4 and ReD-Glk1.
+ * These carry no extra factor: the paper re-discretises with the fine-grid
+ * stencil itself, and only without a factor do the three variants reproduce
+ * the outer iteration counts of its MP-2b table (Section 6) to within one. */
+static cplx row_o2(const lvl_t *g, const cplx *u, int I, int J)
+{
+    size_t P = (size_t)J * g->nx + I;
+    cplx c[5];
+    stencil5(g, 1.0, I, J, c);
+    cplx v = c[0] * u[P];
+    if (c[1] != 0) v += c[1] * u[P - 1];
+    if (c[2] != 0) v += c[2] * u[P + 1];
+    if (c[3] != 0) v += c[3] * u[P - g->nx];
+    if (c[4] != 0) v += c[4] * u[P + g->nx];
+    return v;
+}
+
+/* value of node (I, J), 0 at non-unknowns */
+static cplx uval(const lvl_t *g, const cplx *u, int I, int J)
+{
+    return is_unknown(g, I, J) ? u[(size_t)J * g->nx + I] : 0;
+}
+
+/* ReD-O2 (Section 5.2.2): the fine-grid scheme re-discretised at spacing 2h
+ * on every row. */
+static void coarse_redo2(const hier_t *H, const cplx *u, cplx *y)
+{
+    const lvl_t *g = &H->L[1];
+    for (int J = 0; J < g->ny; J++)
+        for (int I = 0; I < g->nx; I++)
+            y[(size_t)J * g->nx + I] = is_unknown(g, I, J) ? row_o2(g, u, I, J) : 0;
+}
+
+/* ReD-O4 (Section 5.2.2): the Laplacian by fourth-order central differences,
+ * -u'' ~ (u_{i-2} - 16 u_{i-1} + 30 u_i - 16 u_{i+1} + u_{i+2}) / (12 H^2) per
+ * axis, minus k^2 u, at nodes two or more nodes inside the grid; the other
+ * rows (where the wide stencil does not fit) use the second-order scheme with
+ * the boundary closure.  Reading: the printed centre divides k^2 by 12, taken
+ * as a typo for 60/(12 H^2) - k^2 (the consistent fourth-order scheme). */
+static void coarse_redo4(const hier_t *H, const cplx *u, cplx *y)
+{
+    const lvl_t *g = &H->L[1];
+    const double ax = 1.0 / (12.0 * g->hx * g->hx), ay = 1.0 / (12.0 * g->hy * g->hy);
+    for (int J = 0; J < g->ny; J++)
+        for (int I = 0; I < g->nx; I++) {
+            size_t P = (size_t)J * g->nx + I;
+            if (!is_unknown(g, I, J)) {
+                y[P] = 0;
+                continue;
+            }
+            if (I < 2 || J < 2 || I > g->nx - 3 || J > g->ny - 3) {
+                y[P] = row_o2(g, u, I, J);
+                continue;
+            }
+            double kc = g->k[P];
+            cplx lx = uval(g, u, I - 2, J) - 16.0 * uval(g, u, I - 1, J) + 30.0 * u[P] -
+                      16.0 * uval(g, u, I + 1, J) + uval(g, u, I + 2, J);
+            cplx ly = uval(g, u, I, J - 2) - 16.0 * uval(g, u, I, J - 1) + 30.0 * u[P] -
+                      16.0 * uval(g, u, I, J + 1) + uval(g, u, I, J + 2);
+            y[P] = ax * lx + ay * ly - kc * kc * u[P];
+        }
+}
+
+/* ReD-Glk1 (Section 5.2.4): the Galerkin 5x5 stencils of ReD-Glk2 at nodes
+ * two or more nodes inside the grid; the two boundary layers use the
+ * second-order scheme (ReD-O2 rows) instead of ghost elimination. */
+static void coarse_redglk1(const hier_t *H, const cplx *u, cplx *y)
+{
+    const lvl_t *g = &H->L[1];
+    const double H2 = g->hx * g->hx; /* hx == hy checked by the caller */
+    for (int J = 0; J < g->ny; J++)
+        for (int I = 0; I < g->nx; I++) {
+            size_t P = (size_t)J * g->nx + I;
+            if (!is_unknown(g, I, J)) {
+                y[P] = 0;
+                continue;
+            }
+            if (I < 2 || J < 2 || I > g->nx - 3 || J > g->ny - 3) {
+                y[P] = row_o2(g, u, I, J);
+                continue;
+            }
+            cplx v = 0;
+            for (int dJ = -2; dJ <= 2; dJ++)
+                for (int dI = -2; dI <= 2; dI++) {
+                    int Ii = I + dI, Jj = J + dJ;
+                    if (!is_unknown(g, Ii, Jj)) continue;
+                    double lap = GLK_LAP[dJ + 2][dI + 2] / (256.0 * H2);
+                    double kw = GLK_K2[dJ + 2][dI + 2] / 4096.0;
+                    double kc = g->k[(size_t)Jj * g->nx + Ii];
+                    v += (lap - kw * kc * kc) * u[(size_t)Jj * g->nx + Ii];
+                }
+            y[P] = v;
+        }
+}
+
 static void coarse_apply_h(const hier_t *H, const ora_problem *p, const cplx *x, cplx *y)
 {
-    if (p->coarse_op == ORA_COARSE_REDGLK2)
-        coarse_redglk2(H, x, y);
-    else
-        coarse_galerkin(H, p, x, y);
+    switch (p->coarse_op) {
+    case ORA_COARSE_REDGLK2: coarse_redglk2(H, x, y); break;
+    case ORA_COARSE_REDO2: coarse_redo2(H, x, y); break;
+    case ORA_COARSE_REDO4: coarse_redo4(H, x, y); break;
+    case ORA_COARSE_REDGLK1: coarse_redglk1(H, x, y); break;
+    default: coarse_galerkin(H, p, x, y);
+    }
 }
 
 static void coarse_cb(const void *ctx, const cplx *x, cplx *y)
@@ -862,8 +962,10 @@ static int vcycle_l1_cb(void *ctx, const cplx *x, cplx *y)
 static int check_defl(const ora_problem *p, const hier_t *H)
 {
     if (H->nlev < 2) return ORA_EGRID; /* no coarse grid for deflation */
-    if (p->coarse_op == ORA_COARSE_REDGLK2 && p->hx != p->hy) return ORA_EINVAL;
-    if (p->coarse_op != ORA_COARSE_GALERKIN && p->coarse_op != ORA_COARSE_REDGLK2) return ORA_EINVAL;
+    if ((p->coarse_op == ORA_COARSE_REDGLK2 || p->coarse_op == ORA_COARSE_REDGLK1) &&
+        p->hx != p->hy)
+        return ORA_EINVAL;
+    if (p->coarse_op < ORA_COARSE_GALERKIN || p->coarse_op > ORA_COARSE_REDGLK1) return ORA_EINVAL;
     return ORA_OK;
 }
 
@@ -1185,6 +1287,111 @@ done:
     free(y);
     free(sn);
     free(cs);
+    free_hier(&H);
+    return rc;
+}
+
+/* Right-preconditioned GCR(m) with the A-DEF1 preconditioner: the outer
+ * method of Section 6.4 (Eisenstat, Elman and Schultz), which admits a
+ * preconditioner that changes from step to step.  Step j: z = P r,
+ * w = A z; w is made orthogonal to the earlier w_i by modified Gram-Schmidt,
+ * the same combination is applied to z (so w = A z still holds), and both are
+ * divided by ||w||; then alpha = (r, w), x += alpha z, r -= alpha w.  After m
+ * steps the stored pairs are dropped (restart).  When the updated residual
+ * reaches tol ||b|| the true residual is recomputed; the method stops if it
+ * is below tol and otherwise restarts from it.  force_iters > 0 runs exactly
+ * that many steps.  x0 = 0. */
+int ora_gcr(const ora_problem *p, const double *bin, double *xout, int m, double tol, int maxit,
+            int force_iters, ora_info *info)
+{
+    hier_t H;
+    if (m < 1 || maxit < 1) return ORA_EINVAL;
+    int rc = build_hier(p, &H);
+    if (rc) return rc;
+    if ((rc = check_defl(p, &H))) {
+        free_hier(&H);
+        return rc;
+    }
+    const lvl_t *g = &H.L[0];
+    const size_t n = npts(g);
+    cplx *b = (cplx *)malloc(n * sizeof(cplx));
+    cplx *x = (cplx *)xout;
+    cplx *r = (cplx *)malloc(n * sizeof(cplx));
+    cplx *Zs = (cplx *)malloc((size_t)m * n * sizeof(cplx));
+    cplx *Ws = (cplx *)malloc((size_t)m * n * sizeof(cplx));
+    ora_info inf = {0, 0, 0, 0, 0.0};
+    if (!b || !r || !Zs || !Ws) {
+        rc = ORA_ENOMEM;
+        goto done;
+    }
+    memcpy(b, bin, n * sizeof(cplx));
+    mask_unknowns(g, b);
+    for (size_t q = 0; q < n; q++) x[q] = 0;
+    const double bnorm = nrm2(n, b);
+    const int cap = force_iters > 0 ? force_iters : maxit;
+    if (bnorm == 0) {
+        inf.converged = 1;
+        goto done;
+    }
+    for (;;) {
+        /* (re)start from the true residual */
+        op5(g, 1.0, x, r);
+        for (size_t q = 0; q < n; q++) r[q] = b[q] - r[q];
+        inf.relres = nrm2(n, r) / bnorm;
+        if (force_iters <= 0 && inf.relres <= tol) {
+            inf.converged = 1;
+            break;
+        }
+        if (inf.iters >= cap || inf.relres == 0) break;
+        for (int j = 0; j < m && inf.iters < cap; j++) {
+            cplx *zj = Zs + (size_t)j * n, *wj = Ws + (size_t)j * n;
+            int inner = 0;
+            if (p->precond == ORA_PRECOND_EXACT_A) {
+                op5ctx_t c = {g, 1.0};
+                rc = direct_solve_op(g, 1, 1, op5_cb, &c, r, zj);
+            } else {
+                rc = deflate_h(&H, p, ORA_DEFL_ADEF1, r, zj, &inner);
+            }
+            if (rc) goto done;
+            inf.inner_total += inner;
+            if (inner > inf.inner_max) inf.inner_max = inner;
+            op5(g, 1.0, zj, wj);
+            for (int i = 0; i < j; i++) {
+                const cplx *wi = Ws + (size_t)i * n, *zi = Zs + (size_t)i * n;
+                cplx beta = dotc(n, wj, wi);
+                for (size_t q = 0; q < n; q++) {
+                    wj[q] -= beta * wi[q];
+                    zj[q] -= beta * zi[q];
+                }
+            }
+            double nu = nrm2(n, wj);
+            inf.iters++;
+            if (nu == 0) break; /* breakdown: A P r lies in the span already searched */
+            for (size_t q = 0; q < n; q++) {
+                wj[q] /= nu;
+                zj[q] /= nu;
+            }
+            cplx alpha = dotc(n, r, wj);
+            for (size_t q = 0; q < n; q++) {
+                x[q] += alpha * zj[q];
+                r[q] -= alpha * wj[q];
+            }
+            if (force_iters <= 0 && nrm2(n, r) <= tol * bnorm) break;
+        }
+        if (force_iters > 0 && inf.iters >= cap) {
+            op5(g, 1.0, x, r);
+            for (size_t q = 0; q < n; q++) r[q] = b[q] - r[q];
+            inf.relres = nrm2(n, r) / bnorm;
+            inf.converged = inf.relres <= tol;
+            break;
+        }
+    }
+done:
+    if (info) *info = inf;
+    free(b);
+    free(r);
+    free(Zs);
+    free(Ws);
     free_hier(&H);
     return rc;
 }

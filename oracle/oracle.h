@@ -39,7 +39,13 @@ extern "C" {
 
 enum { ORA_BC_DIRICHLET = 0, ORA_BC_SOMMERFELD = 1 };
 enum { ORA_Z_LINEAR = 0, ORA_Z_HIGH = 1 };
-enum { ORA_COARSE_GALERKIN = 0, ORA_COARSE_REDGLK2 = 1 };
+enum {
+    ORA_COARSE_GALERKIN = 0, /* str-Glk: Z^T A_h Z                       */
+    ORA_COARSE_REDGLK2 = 1,  /* Galerkin 5x5 stencils, ghost-point band     */
+    ORA_COARSE_REDO2 = 2,    /* second-order re-discretisation            */
+    ORA_COARSE_REDO4 = 3,    /* fourth-order re-discretisation            */
+    ORA_COARSE_REDGLK1 = 4   /* Galerkin 5x5 stencils, second-order band    */
+};
 enum { ORA_CMODE_EXACT = 0, ORA_CMODE_FIXED = 1, ORA_CMODE_TOL = 2 };
 enum { ORA_DEFL_Q = 0, ORA_DEFL_P = 1, ORA_DEFL_ADEF1 = 2 };
 enum { ORA_PRECOND_VCYCLE = 0, ORA_PRECOND_EXACT_A = 1 };
@@ -98,6 +104,10 @@ int ora_deflate_apply(const ora_problem *p, int mode, const double *v, double *w
  * force_iters > 0 runs exactly that many iterations (no tolerance test). */
 int ora_fgmres(const ora_problem *p, const double *b, double *x, int restart,
                double tol, int maxit, int force_iters, ora_info *info);
+/* Right-preconditioned GCR(restart) with the A-DEF1 preconditioner (the
+ * variable-preconditioner outer method of Section 6.4). */
+int ora_gcr(const ora_problem *p, const double *b, double *x, int restart, double tol,
+            int maxit, int force_iters, ora_info *info);
 /* The paper's left-preconditioned full GMRES (Algorithm 1, no restart),
  * stopping on the preconditioned relative residual. */
 int ora_gmres_left(const ora_problem *p, const double *b, double *x, double tol,

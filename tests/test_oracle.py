@@ -543,3 +543,160 @@ def test_level_hierarchy(ora):
     assert ora.num_levels(37, 53) == 3  # 37x53 -> 19x27 -> 10x14 (even: stop)
     assert ora.level_dims(37, 53, 2) == (10, 14)
     assert ora.num_levels(4, 9) == 1
+
+
+# ---------------------------------------------------------------------------
+# Coarse-operator variants (Section 5.2.2, 5.2.4) and the GCR outer method
+# (Section 6.4)
+# ---------------------------------------------------------------------------
+def _poly_cases(X, Y):
+    """(u, -Lap u) pairs of polynomials."""
+    return [
+        (X ** 3 + 2 * X * Y, -6 * X),
+        (X ** 2 * Y + Y ** 3, -2 * Y - 6 * Y),
+        (X ** 5 - 3 * Y ** 4, -20 * X ** 3 + 36 * Y ** 2),
+        (X ** 4 * Y ** 2 + X * Y ** 5, -(12 * X ** 2 * Y ** 2 + 2 * X ** 4) - 20 * X * Y ** 3),
+    ]
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_redo2_and_redo4_taylor(ora, bc):
+    """ReD-O2 is exact on cubics and ReD-O4 on quintics (per axis) at the
+    rows where each applies: A_2h u = -Lap u - k^2 u.  ReD-O4's rows next to
+    the boundary are the second-order rows."""
+    n, k = 33, 5.0
+    p2 = _prob(ora, n, k, bc, coarse_op=ora.COARSE_REDO2)
+    p4 = p2.replace(coarse_op=ora.COARSE_REDO4)
+    nxc, nyc = ora.coarse_dims(p2)
+    H = 2 * p2.hx
+    X, Y = np.meshgrid(np.arange(nxc) * H, np.arange(nyc) * H)
+    in1 = (slice(1, nyc - 1), slice(1, nxc - 1))
+    in2 = (slice(2, nyc - 2), slice(2, nxc - 2))
+    for idx, (u, lap) in enumerate(_poly_cases(X, Y)):
+        want = lap - k * k * u
+        if bc == 0:  # Dirichlet: homogeneous boundary, so only check away from it
+            u = _interior(u + 0j)
+        got2 = ora.coarse_apply(p2, u + 0j)
+        got4 = ora.coarse_apply(p4, u + 0j)
+        sc = np.abs(want[in2]).max()
+        s2 = (slice(2, nyc - 2), slice(2, nxc - 2)) if bc == 0 else in1
+        if idx < 2:  # cubics: both exact
+            assert np.abs(got2[s2] - want[s2]).max() <= 1e-9 * sc
+        # fourth order: exact for every case at rows >= 2 from the boundary
+        s4 = (slice(3, nyc - 3), slice(3, nxc - 3)) if bc == 0 else in2
+        assert np.abs(got4[s4] - want[s4]).max() <= 1e-9 * sc
+        # the ring of near-boundary rows of ReD-O4 equals ReD-O2
+        ring = np.zeros((nyc, nxc), bool)
+        ring[:2, :] = ring[-2:, :] = ring[:, :2] = ring[:, -2:] = True
+        assert np.abs(got4[ring] - got2[ring]).max() <= 1e-12 * np.abs(got2).max()
+    # ReD-O2 is the second-order operator at spacing 2h, boundary rows
+    # included: compare against the fine-grid operator on a grid of spacing 2h
+    pc = _prob(ora, nxc, k, bc)
+    pc = pc.replace(hx=H, hy=H)
+    u = inputs.random_complex((nyc, nxc), 21)
+    if bc == 0:
+        u = _interior(u)
+    assert np.abs(ora.coarse_apply(p2, u) - ora.helm_apply(pc, u)).max() <= \
+        1e-12 * np.abs(ora.coarse_apply(p2, u)).max()
+
+
+def test_redo4_printed_centre_reading(ora):
+    """The centre weight of ReD-O4 is 60/(12 H^2) - k^2: the k^2 coefficient is
+    not divided by 12 as printed (reading of Section 5.2.2; the printed form
+    would not be consistent with -Lap - k^2)."""
+    n, k = 33, 7.0
+    p = _prob(ora, n, k, 1, coarse_op=ora.COARSE_REDO4)
+    nxc, nyc = ora.coarse_dims(p)
+    H = 2 * p.hx
+    e = np.zeros((nyc, nxc), complex)
+    e[8, 8] = 1
+    col = ora.coarse_apply(p, e)
+    assert abs(col[8, 8] - (60 / (12 * H * H) - k * k)) <= 1e-12 * abs(col[8, 8])
+    assert abs(col[8, 9] - (-16 / (12 * H * H))) <= 1e-12 * abs(col[8, 8])
+    assert abs(col[8, 10] - (1 / (12 * H * H))) <= 1e-12 * abs(col[8, 8])
+    assert col[9, 9] == 0 and col[8, 11] == 0
+
+
+def test_redglk1_rows(ora):
+    """ReD-Glk1 (Section 5.2.4): the interior rows are ReD-Glk2's (the Galerkin
+    5x5 stencils); the two boundary layers are the second-order rows of
+    ReD-O2."""
+    n, k = 33, 6.0
+    for bc in (0, 1):
+        p1 = _prob(ora, n, k, bc, coarse_op=ora.COARSE_REDGLK1)
+        p2 = p1.replace(coarse_op=ora.COARSE_REDGLK2)
+        po = p1.replace(coarse_op=ora.COARSE_REDO2)
+        nxc, nyc = ora.coarse_dims(p1)
+        u = inputs.random_complex((nyc, nxc), 22)
+        if bc == 0:
+            u = _interior(u)
+        a1, a2, ao = ora.coarse_apply(p1, u), ora.coarse_apply(p2, u), ora.coarse_apply(po, u)
+        inner = (slice(2, nyc - 2), slice(2, nxc - 2))
+        # ReD-Glk2's second layer differs (ghost elimination); compare deeper
+        deep = (slice(3, nyc - 3), slice(3, nxc - 3))
+        assert np.abs(a1[deep] - a2[deep]).max() <= 1e-12 * np.abs(a2).max()
+        ring = np.ones((nyc, nxc), bool)
+        ring[inner] = False
+        assert np.abs(a1[ring] - ao[ring]).max() <= 1e-12 * np.abs(ao).max()
+        # Glk1 on the second layer reaches only grid nodes: the Glk interior
+        # stencil applied where it fits, checked against a direct evaluation
+        # at one second-layer-adjacent node (I, J) = (2, 5)
+        H = 2 * p1.hx
+        e = np.zeros((nyc, nxc), complex)
+        e[5, 0] = 1
+        col = ora.coarse_apply(p1, e)
+        # row (5, 2) couples to (5, 0) with the printed weights at dI = -2
+        lap = -98 / (256 * H * H)
+        kw = 70 / 4096
+        if bc == 1:
+            assert abs(col[5, 2] - (lap - kw * k * k)) <= 1e-12 * abs(lap)
+        else:
+            assert col[5, 2] == 0  # (5, 0) is a Dirichlet boundary node
+
+
+def test_redglk_variants_rejected_for_unequal_spacing(ora):
+    nx, ny = 17, 17
+    for cop, ok in ((ora.COARSE_REDGLK1, False), (ora.COARSE_REDGLK2, False),
+                    (ora.COARSE_REDO2, True), (ora.COARSE_REDO4, True)):
+        p = ora.Problem(nx, ny, 0.1, 0.2, bc=1, kconst=2.0, coarse_op=cop)
+        if ok:
+            ora.coarse_apply(p, np.ones((9, 9), complex))
+        else:
+            with pytest.raises(ora.OracleError):
+                ora.coarse_apply(p, np.ones((9, 9), complex))
+
+
+@pytest.mark.parametrize("bc,cop", [(0, 0), (1, 1), (1, 3)])
+def test_gcr_matches_fgmres_for_a_fixed_preconditioner(ora, bc, cop):
+    """With a linear preconditioner (exact coarse solve: P_A-DEF1 is then a
+    fixed matrix) GCR and FGMRES minimise the same residual over the same space
+    P K_j(A P, r0), so their residual histories agree to rounding.  An
+    independent pin of the GCR recurrences against the Arnoldi/Givens path."""
+    n, k = 33, 12.0
+    p = _prob(ora, n, k, bc, coarse_op=cop, coarse_mode=ora.CMODE_EXACT)
+    b = inputs.point_source(n, n, p.hx, p.hy, n // 2, n // 2)
+    for it in (1, 3, 5):
+        _, ig = ora.gcr(p, b, restart=50, force_iters=it)
+        _, if_ = ora.fgmres(p, b, restart=50, force_iters=it)
+        assert ig.iters == if_.iters == it
+        assert abs(ig.relres - if_.relres) <= 1e-9 * if_.relres
+
+
+def test_gcr_solves_to_direct_solution(ora):
+    n, k = 33, 10.0
+    p = _prob(ora, n, k, 1, coarse_op=ora.COARSE_REDGLK2)
+    b = inputs.point_source(n, n, p.hx, p.hy, 16, 16)
+    x, inf = ora.gcr(p, b, restart=50, tol=1e-12, maxit=300)
+    xd = ora.direct_solve(p, b)
+    assert inf.converged and inf.relres <= 1e-12
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-9
+    # restarted GCR still converges (more iterations)
+    x4, inf4 = ora.gcr(p, b, restart=4, tol=1e-12, maxit=400)
+    assert inf4.converged and inf4.iters >= inf.iters
+
+
+def test_gcr_exact_preconditioner_one_iteration(ora):
+    p = _prob(ora, 17, 5.0, 1, precond=ora.PRECOND_EXACT_A, coarse_mode=ora.CMODE_EXACT)
+    b = inputs.random_complex((17, 17), 23)
+    _, inf = ora.gcr(p, b, tol=1e-10)
+    assert inf.converged and inf.iters == 1
