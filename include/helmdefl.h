@@ -51,7 +51,23 @@ typedef enum {
 enum { HELM_BC_DIRICHLET = 0, HELM_BC_SOMMERFELD = 1 };
 enum { HELM_DEFL_Q = 0, HELM_DEFL_P = 1, HELM_DEFL_ADEF1 = 2 };
 enum { HELM_Z_LINEAR = 0, HELM_Z_HIGH = 1 };
-enum { HELM_COARSE_GALERKIN = 0, HELM_COARSE_REDGLK2 = 1 };
+/* Coarse-grid operators A_2h (Section 5.2): str-Glk (Z^T A_h Z, Section
+ * 5.2.1); ReD-Glk2 and ReD-Glk1 (the Galerkin 5x5 stencils re-used as a
+ * coarse discretisation, with ghost-point or second-order boundary rows,
+ * Section 5.2.4); ReD-O2 and ReD-O4 (second- and fourth-order
+ * re-discretisation, Section 5.2.2).  ReD-Glk* need hx == hy. */
+enum {
+    HELM_COARSE_GALERKIN = 0,
+    HELM_COARSE_REDGLK2 = 1,
+    HELM_COARSE_REDO2 = 2,
+    HELM_COARSE_REDO4 = 3,
+    HELM_COARSE_REDGLK1 = 4
+};
+/* Outer Krylov methods: flexible GMRES (right preconditioning, true residual
+ * test; the default), GCR (right preconditioning, Section 6.4), and the
+ * paper's left-preconditioned GMRES of Algorithm 1 (restarted after
+ * `restart` steps; stops on the preconditioned residual relative to ||P b||). */
+enum { HELM_OUTER_FGMRES = 0, HELM_OUTER_GCR = 1, HELM_OUTER_GMRES_LEFT = 2 };
 enum { HELM_CMODE_FIXED = 1, HELM_CMODE_TOL = 2 };
 enum { HELM_PREC_FP64 = 0, HELM_PREC_MIXED = 1 };
 
@@ -93,6 +109,7 @@ typedef struct {
                                 coarse GMRES and that solve's own V-cycle) and
                                 the residual test stay FP64; FGMRES absorbs the
                                 perturbed preconditioner (Section 5.2). */
+    int outer;               /* HELM_OUTER_* (default HELM_OUTER_FGMRES)       */
 } helm_opts;
 
 /* Per right-hand side result of helm_solve. */
@@ -100,7 +117,8 @@ typedef struct {
     int outer_iters;       /* preconditioner applications, over all restarts     */
     int inner_iters_total; /* coarse-grid GMRES iterations, summed               */
     int inner_iters_max;   /* largest single coarse solve                        */
-    int converged;         /* relres <= tol                                      */
+    int converged;         /* relres <= tol (GMRES_LEFT: the preconditioned
+                              residual test of Algorithm 1 was met)             */
     double relres;         /* ||b - A x|| / ||b|| recomputed in FP64 at exit     */
     double t_solve_ms;     /* wall time of this right-hand side                  */
 } helm_solve_info;
@@ -149,7 +167,8 @@ int deflate_apply(helm_ctx *h, int mode, const void *v, void *w, int nrhs);
 
 /* Solve A_h x = b by flexible GMRES(restart), right-preconditioned with
  * P_A-DEF1, to ||b - A x|| / ||b|| <= tol (true residual, checked at every
- * restart).  x: output, and input when opts.x0_given.  info: array of nrhs
+ * restart); or by GCR(restart) or the left-preconditioned GMRES of
+ * Algorithm 1, per opts.outer.  x: output, and input when opts.x0_given.  info: array of nrhs
  * entries, may be NULL.  HELM_ENOCONV when maxit was reached above tol; x then
  * holds the last iterate and info is filled.  HELM_ENONFINITE if b is not
  * finite. */

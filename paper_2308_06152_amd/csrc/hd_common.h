@@ -139,8 +139,12 @@ hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf,
 // t = v - A_h (Z v2).
 hipError_t launch_dresid(const Lev &Lf, const Lev &Lc, int zho, const cd *v, const cd *v2,
                          cd *t, hipStream_t st);
-// y = A_2h x (ReD-Glk2) or y = b - A_2h x; interior and boundary band.
-hipError_t launch_redglk2(const Lev &Lc, const cd *x, const cd *b, cd *y, hipStream_t st);
+// y = A_2h x (ReD-Glk2, or ReD-Glk1 when glk1) or y = b - A_2h x; interior
+// and boundary band.
+hipError_t launch_redglk2(const Lev &Lc, const cd *x, const cd *b, cd *y, int glk1,
+                          hipStream_t st);
+// y = A_2h x (ReD-O4) or y = b - A_2h x.
+hipError_t launch_redo4(const Lev &Lc, const cd *x, const cd *b, cd *y, hipStream_t st);
 
 // ---- Krylov kernels ----
 // Number of partial-sum blocks used for vectors of length n.

@@ -136,6 +136,7 @@ struct helm_ctx {
     // outer FGMRES (allocated on first solve)
     int m = 0;
     cd *V = nullptr, *Z = nullptr, *w = nullptr, *bm = nullptr;
+    cd *w2 = nullptr, *r = nullptr;  // GCR / left GMRES work vectors
 
     // kernel timing
     int t_cls = -1, t_lev = -1;
@@ -435,9 +436,14 @@ int coarse_apply(helm_ctx *h, const cd *x, const cd *b, cd *y)
 {
     const Lev Lf = h->lev(0), Lc = h->lev(1);
     const size_t nc = h->L[1].n(), nf = h->L[0].n();
-    if (h->o.coarse_op == HELM_COARSE_REDGLK2) {
+    if (h->o.coarse_op != HELM_COARSE_GALERKIN) {
         Timed tm(h, HELM_K_COARSE, 1, (b ? 48.0 : 32.0) * nc);
-        HCHK(launch_redglk2(Lc, x, b, y, h->st));
+        switch (h->o.coarse_op) {
+        case HELM_COARSE_REDGLK2: HCHK(launch_redglk2(Lc, x, b, y, 0, h->st)); break;
+        case HELM_COARSE_REDGLK1: HCHK(launch_redglk2(Lc, x, b, y, 1, h->st)); break;
+        case HELM_COARSE_REDO4: HCHK(launch_redo4(Lc, x, b, y, h->st)); break;
+        default: HCHK(launch_apply5(Lc, make_double2(1.0, 0.0), x, b, y, h->st));  // ReD-O2
+        }
         return HELM_OK;
     }
     Timed tm(h, HELM_K_COARSE, 1, (b ? 48.0 : 32.0) * nc + 64.0 * nf);
@@ -554,14 +560,18 @@ int ensure_outer(helm_ctx *h)
     if (h->V) return HELM_OK;
     const size_t n = h->L[0].n();
     const int m = h->o.restart;
+    const bool extra = h->o.outer != HELM_OUTER_FGMRES;
     int rc;
     if ((rc = dalloc(&h->V, (size_t)(m + 1) * n)) || (rc = dalloc(&h->Z, (size_t)m * n)) ||
-        (rc = dalloc(&h->w, n)) || (rc = dalloc(&h->bm, n))) {
+        (rc = dalloc(&h->w, n)) || (rc = dalloc(&h->bm, n)) ||
+        (extra && ((rc = dalloc(&h->w2, n)) || (rc = dalloc(&h->r, n))))) {
         dfree(h->V);
         dfree(h->Z);
         dfree(h->w);
         dfree(h->bm);
-        h->V = h->Z = h->w = h->bm = nullptr;
+        dfree(h->w2);
+        dfree(h->r);
+        h->V = h->Z = h->w = h->bm = h->w2 = h->r = nullptr;
         return rc;
     }
     h->m = m;
@@ -638,6 +648,198 @@ int solve_one(helm_ctx *h, const cd *b, cd *x, helm_solve_info *info)
             }
         }
         if (!inf.converged && force <= 0) rc = HELM_ENOCONV;
+    }
+    HCHK(hipStreamSynchronize(h->st));
+    inf.t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return rc;
+}
+
+// Read back the norm left by a mode-2 reduction in hbuf[2*PSTRIDE] (sync).
+int read_norm(helm_ctx *h, double *out)
+{
+    HCHK(hipMemcpyAsync(h->hpin + PIN_NORM, h->hbuf + 2 * PSTRIDE, sizeof(cd),
+                        hipMemcpyDeviceToHost, h->st));
+    HCHK(hipStreamSynchronize(h->st));
+    *out = h->hpin[PIN_NORM].x;
+    return HELM_OK;
+}
+
+// Right-preconditioned GCR(m) (Section 6.4; the method of Eisenstat, Elman
+// and Schultz), preconditioner P_A-DEF1.  Step j: z = P r, w = A z; w is
+// orthogonalised against W[0..j-1] (the same Gram-Schmidt pass as the Arnoldi
+// steps, with its conditional second pass) and the same coefficients are
+// applied to z, so w = A z is kept; both are divided by ||w|| into W[j], Z[j];
+// then alpha = W[j]^H r, x += alpha Z[j], r -= alpha W[j].  The pairs are
+// dropped after m steps (restart from the true residual); when the updated
+// residual reaches tol ||b|| the true residual decides.
+int solve_gcr(helm_ctx *h, const cd *b, cd *x, helm_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t n = h->L[0].n();
+    const int m = h->m, nb = krylov_blocks(n);
+    const Lev L0 = h->lev(0);
+    const int force = h->o.force_iters;
+    const int cap = force > 0 ? force : h->o.maxit;
+    cd *W = h->V, *Zs = h->Z, *r = h->r, *z = h->w2, *w = h->w;
+    cd *h1 = h->hbuf, *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
+    helm_solve_info inf{};
+    HCHK(launch_mask_copy(L0, b, h->bm, h->st));
+    double bnorm;
+    RCHK(vnorm(h, h->bm, n, &bnorm));
+    if (!std::isfinite(bnorm)) return HELM_ENONFINITE;
+    if (h->o.x0_given)
+        HCHK(launch_mask_copy(L0, x, x, h->st));
+    else
+        HCHK(launch_zero(x, n, h->st));
+    int rc = HELM_OK;
+    std::vector<zc> col(m + 1);
+    if (bnorm == 0.0) {
+        HCHK(launch_zero(x, n, h->st));
+        inf.converged = 1;
+    } else {
+        for (;;) {
+            RCHK(apply_A(h, 0, x, h->bm, r));
+            double rn;
+            RCHK(vnorm(h, r, n, &rn));
+            inf.relres = rn / bnorm;
+            if (force <= 0 && inf.relres <= h->o.tol) {
+                inf.converged = 1;
+                break;
+            }
+            if (inf.outer_iters >= cap || rn == 0.0) break;
+            for (int j = 0; j < m && inf.outer_iters < cap; j++) {
+                int inner = 0;
+                RCHK(deflate_one(h, HELM_DEFL_ADEF1, r, z, &inner));
+                inf.inner_iters_total += inner;
+                if (inner > inf.inner_iters_max) inf.inner_iters_max = inner;
+                RCHK(apply_A(h, 0, z, nullptr, w));
+                double nu;
+                if (j == 0) {
+                    RCHK(vnorm(h, w, n, &nu));
+                    HCHK(launch_scale(w, nr, W, n, h->st));
+                } else {
+                    RCHK(arnoldi_step(h, W, n, j, w, n, col.data(), &nu, 0));
+                    HCHK(launch_mupdate(z, Zs, n, j, h1, n, nullptr, nullptr, 0, nullptr, h->st));
+                    HCHK(launch_mupdate(z, Zs, n, j, h2, n, nullptr, h1, j, nullptr, h->st));
+                }
+                HCHK(launch_scale(z, nr, Zs + (size_t)j * n, n, h->st));
+                inf.outer_iters++;
+                if (nu == 0.0) break;  // A P r already lies in the searched space
+                cd *Wj = W + (size_t)j * n, *Zj = Zs + (size_t)j * n;
+                HCHK(launch_mdot(Wj, n, 1, r, n, h->part, 0, nullptr, 0, h->st));
+                HCHK(launch_reduce(h->part, nb, 1, h->ydev, 0, nullptr, 0, nullptr, 0, nullptr,
+                                   h->st));
+                HCHK(launch_lincomb(Zj, n, 1, h->ydev, x, n, 1, h->st));
+                HCHK(launch_mupdate(r, Wj, n, 1, h->ydev, n, h->partn, nullptr, 0, nullptr,
+                                    h->st));
+                HCHK(launch_reduce(h->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, nullptr,
+                                   h->st));
+                RCHK(read_norm(h, &rn));
+                if (std::getenv("HELMDEFL_LOG"))
+                    std::fprintf(stderr, "helmdefl: gcr it %d  relres %.3e  inner %d\n",
+                                 inf.outer_iters, rn / bnorm, inner);
+                if (force <= 0 && rn <= h->o.tol * bnorm) break;
+            }
+            if (force > 0 && inf.outer_iters >= cap) {
+                RCHK(apply_A(h, 0, x, h->bm, r));
+                RCHK(vnorm(h, r, n, &rn));
+                inf.relres = rn / bnorm;
+                inf.converged = inf.relres <= h->o.tol;
+                break;
+            }
+        }
+        if (!inf.converged && force <= 0) rc = HELM_ENOCONV;
+    }
+    HCHK(hipStreamSynchronize(h->st));
+    inf.t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return rc;
+}
+
+// The paper's left-preconditioned deflated GMRES (Algorithm 1) on
+// P A x = P b, P = P_A-DEF1: v_1 = P (b - A x0) / ||.||, each step w = P (A v_j)
+// orthogonalised against V (the Arnoldi step above), stopping when the
+// preconditioned residual |g_{j+1}| drops to tol ||P b||.  Restarted after
+// `restart` steps from the current x.  The non-singular A-DEF1 needs no final
+// projection.  info.relres is the true residual at exit.
+int solve_left(helm_ctx *h, const cd *b, cd *x, helm_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const size_t n = h->L[0].n();
+    const int m = h->m;
+    const Lev L0 = h->lev(0);
+    const int cap = h->o.maxit;
+    cd *nr = h->hbuf + 2 * PSTRIDE;
+    helm_solve_info inf{};
+    HCHK(launch_mask_copy(L0, b, h->bm, h->st));
+    double bnorm;
+    RCHK(vnorm(h, h->bm, n, &bnorm));
+    if (!std::isfinite(bnorm)) return HELM_ENONFINITE;
+    if (h->o.x0_given)
+        HCHK(launch_mask_copy(L0, x, x, h->st));
+    else
+        HCHK(launch_zero(x, n, h->st));
+    int rc = HELM_OK;
+    if (bnorm == 0.0) {
+        HCHK(launch_zero(x, n, h->st));
+        inf.converged = 1;
+    } else {
+        Givens gv(m);
+        std::vector<zc> col(m + 1), y;
+        double beta0 = -1.0;
+        for (;;) {
+            int inner = 0;
+            RCHK(apply_A(h, 0, x, h->bm, h->w));
+            RCHK(deflate_one(h, HELM_DEFL_ADEF1, h->w, h->w2, &inner));
+            inf.inner_iters_total += inner;
+            if (inner > inf.inner_iters_max) inf.inner_iters_max = inner;
+            double beta;
+            RCHK(vnorm(h, h->w2, n, &beta));
+            if (beta0 < 0) beta0 = beta;
+            if (beta <= h->o.tol * beta0 || beta == 0.0) {
+                inf.converged = 1;
+                break;
+            }
+            if (inf.outer_iters >= cap) break;
+            HCHK(launch_scale(h->w2, nr, h->V, n, h->st));
+            gv.start(beta);
+            int jend = 0;
+            bool done = false;
+            for (int j = 0; j < m && inf.outer_iters < cap; j++) {
+                RCHK(apply_A(h, 0, h->V + (size_t)j * n, nullptr, h->w));
+                RCHK(deflate_one(h, HELM_DEFL_ADEF1, h->w, h->w2, &inner));
+                inf.inner_iters_total += inner;
+                if (inner > inf.inner_iters_max) inf.inner_iters_max = inner;
+                double hn;
+                RCHK(arnoldi_step(h, h->V, n, j + 1, h->w2, n, col.data(), &hn, 0));
+                const double res = gv.add_column(j, col.data(), hn);
+                inf.outer_iters++;
+                jend = j + 1;
+                if (std::getenv("HELMDEFL_LOG"))
+                    std::fprintf(stderr, "helmdefl: left it %d  prec relres %.3e  inner %d\n",
+                                 inf.outer_iters, res / beta0, inner);
+                if (res <= h->o.tol * beta0) {
+                    done = true;
+                    break;
+                }
+                if (hn == 0.0) break;
+            }
+            gv.solve(jend, y);
+            RCHK(upload_y(h, y));
+            HCHK(launch_lincomb(h->V, n, jend, h->ydev, x, n, 1, h->st));
+            if (done) {
+                inf.converged = 1;
+                break;
+            }
+        }
+        RCHK(apply_A(h, 0, x, h->bm, h->w));
+        double rn;
+        RCHK(vnorm(h, h->w, n, &rn));
+        inf.relres = rn / bnorm;
+        if (!inf.converged) rc = HELM_ENOCONV;
     }
     HCHK(hipStreamSynchronize(h->st));
     inf.t_solve_ms =
@@ -755,6 +957,8 @@ void release(helm_ctx *h)
     dfree(h->Z);
     dfree(h->w);
     dfree(h->bm);
+    dfree(h->w2);
+    dfree(h->r);
     if (h->hpin) (void)hipHostFree(h->hpin);
     dfree(h->sig);
     for (auto e : h->ev_slot)
@@ -782,9 +986,12 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (o.nu_pre != 1 || o.nu_post != 1) return HELM_EINVAL;
     if (!(o.omega > 0) || !std::isfinite(o.beta_re) || !std::isfinite(o.beta_im)) return HELM_EINVAL;
     if (o.defl_vectors != HELM_Z_LINEAR && o.defl_vectors != HELM_Z_HIGH) return HELM_EINVAL;
-    if (o.coarse_op != HELM_COARSE_GALERKIN && o.coarse_op != HELM_COARSE_REDGLK2)
+    if (o.coarse_op < HELM_COARSE_GALERKIN || o.coarse_op > HELM_COARSE_REDGLK1)
         return HELM_EINVAL;
-    if (o.coarse_op == HELM_COARSE_REDGLK2 && g->hx != g->hy) return HELM_EINVAL;
+    if ((o.coarse_op == HELM_COARSE_REDGLK2 || o.coarse_op == HELM_COARSE_REDGLK1) &&
+        g->hx != g->hy)
+        return HELM_EINVAL;
+    if (o.outer < HELM_OUTER_FGMRES || o.outer > HELM_OUTER_GMRES_LEFT) return HELM_EINVAL;
     if (o.coarse_mode != HELM_CMODE_FIXED && o.coarse_mode != HELM_CMODE_TOL) return HELM_EINVAL;
     if (o.coarse_iters < 1 || o.coarse_restart < 1 || o.coarse_restart > MAX_RESTART)
         return HELM_EINVAL;
@@ -930,6 +1137,7 @@ int helm_opts_default(helm_opts *o)
     o->force_iters = 0;
     o->coarsest_nodes = 1089;
     o->precision = HELM_PREC_FP64;
+    o->outer = HELM_OUTER_FGMRES;
     return HELM_OK;
 }
 
@@ -990,8 +1198,12 @@ int helm_solve(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *i
     try {
         RCHK(ensure_outer(h));
         for (int q = 0; q < nrhs; q++) {
-            const int rc = solve_one(h, (const cd *)b + q * n, (cd *)x + q * n,
-                                     info ? info + q : nullptr);
+            const cd *bq = (const cd *)b + q * n;
+            cd *xq = (cd *)x + q * n;
+            helm_solve_info *iq = info ? info + q : nullptr;
+            const int rc = h->o.outer == HELM_OUTER_GCR         ? solve_gcr(h, bq, xq, iq)
+                           : h->o.outer == HELM_OUTER_GMRES_LEFT ? solve_left(h, bq, xq, iq)
+                                                                 : solve_one(h, bq, xq, iq);
             if (rc != HELM_OK && rc != HELM_ENOCONV) return rc;
             if (rc == HELM_ENOCONV) worst = rc;
         }

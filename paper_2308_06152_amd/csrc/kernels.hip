@@ -898,11 +898,12 @@ __device__ __forceinline__ cd ghost_y(const Lev &L, const cd *u, int I, int Jg)
 // = the 5x5 stencil with ghost nodes eliminated (k = 0 at ghosts; a ghost
 // outside in both directions is the mean of its two single-direction
 // neighbours).  Dirichlet boundary nodes are not unknowns.
+// ReD-Glk1 (GLK1): both layers are the plain second-order 5-point rows.
 // Band layout: nR boundary-band rows (0, 1, ny-2, ny-1 without repeats; all
 // rows when ny < 5) cover every column; then nC band columns cover the rows
 // 2..ny-3 in between.  Band row k is k for k < 2, else ny - nR + k (columns
 // alike).  blk numbers the band's own blocks.
-template <bool RESID>
+template <bool RESID, bool GLK1>
 __device__ __forceinline__ void redglk2_band(const Lev &L, const cd *__restrict__ u,
                                              const cd *__restrict__ b, cd *__restrict__ y,
                                              int nR, int nC, int count, int blk)
@@ -923,7 +924,7 @@ __device__ __forceinline__ void redglk2_band(const Lev &L, const cd *__restrict_
     const size_t p = (size_t)J * L.nx + I;
     cd o = czero();
     if (unknown(L, I, J)) {
-        const bool bnd = I == 0 || J == 0 || I == L.nx - 1 || J == L.ny - 1;
+        const bool bnd = GLK1 || I == 0 || J == 0 || I == L.nx - 1 || J == L.ny - 1;
         if (bnd) {
             cd ap;
             double aw, ae, as, an;
@@ -933,7 +934,7 @@ __device__ __forceinline__ void redglk2_band(const Lev &L, const cd *__restrict_
             if (ae != 0.0) caxpy(o, ae, u[p + 1]);
             if (as != 0.0) caxpy(o, as, u[p - L.nx]);
             if (an != 0.0) caxpy(o, an, u[p + L.nx]);
-            o = cscal(4.0, o);
+            if (!GLK1) o = cscal(4.0, o);
         } else {
             const double iH2 = L.ihx2;
             for (int dJ = -2; dJ <= 2; dJ++)
@@ -962,7 +963,7 @@ __device__ __forceinline__ void redglk2_band(const Lev &L, const cd *__restrict_
 
 // One launch for the whole coarse operator: blocks [0, nb_int) do interior
 // tiles, the blocks after them the boundary band, so both run concurrently.
-template <bool RESID, bool VARK>
+template <bool RESID, bool VARK, bool GLK1>
 __global__ __launch_bounds__(256) void k_redglk2(Lev L, const cd *__restrict__ u,
                                                  const cd *__restrict__ b, cd *__restrict__ y,
                                                  int tiles_x, int nb_int, int nR, int nC,
@@ -971,10 +972,11 @@ __global__ __launch_bounds__(256) void k_redglk2(Lev L, const cd *__restrict__ u
     if ((int)blockIdx.x < nb_int)
         redglk2_interior<RESID, VARK>(L, u, b, y, tiles_x, nb_int);
     else
-        redglk2_band<RESID>(L, u, b, y, nR, nC, count, blockIdx.x - nb_int);
+        redglk2_band<RESID, GLK1>(L, u, b, y, nR, nC, count, blockIdx.x - nb_int);
 }
 
-hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, hipStream_t st)
+template <bool GLK1>
+static hipError_t redglk_t(const Lev &L, const cd *x, const cd *b, cd *y, hipStream_t st)
 {
     int tx = 0, nb_int = 0;
     if (L.nx >= 5 && L.ny >= 5) {
@@ -988,15 +990,79 @@ hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, hipStre
     const int nb = nb_int + cdiv(count, 256);
     if (L.k) {
         if (b)
-            k_redglk2<true, true><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
+            k_redglk2<true, true, GLK1><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
         else
-            k_redglk2<false, true><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
+            k_redglk2<false, true, GLK1><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC,
+                                                            count);
     } else {
         if (b)
-            k_redglk2<true, false><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
+            k_redglk2<true, false, GLK1><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC,
+                                                            count);
         else
-            k_redglk2<false, false><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
+            k_redglk2<false, false, GLK1><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC,
+                                                             count);
     }
+    HD_LAUNCH_CHECK();
+}
+
+hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, int glk1, hipStream_t st)
+{
+    return glk1 ? redglk_t<true>(L, x, b, y, st) : redglk_t<false>(L, x, b, y, st);
+}
+
+// ------------------------------------------------------------------------
+// ReD-O4 coarse operator (Section 5.2.2): fourth-order central differences
+// for the Laplacian, (u_{i-2} - 16 u_{i-1} + 30 u_i - 16 u_{i+1} + u_{i+2}) /
+// (12 H^2) per axis, minus k^2 u, at nodes two or more nodes inside the
+// grid; the other rows are the second-order 5-point rows with the boundary
+// closure.  One thread per node; the 9 reads of a row come through L1/L2.
+// ------------------------------------------------------------------------
+template <bool RESID>
+__global__ __launch_bounds__(256) void k_redo4(Lev L, const cd *__restrict__ u,
+                                               const cd *__restrict__ b, cd *__restrict__ y,
+                                               int tiles_x)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int I = (t % tiles_x) * 64 + (threadIdx.x & 63);
+    const int J = (t / tiles_x) * 4 + (threadIdx.x >> 6);
+    if (I >= L.nx || J >= L.ny) return;
+    const size_t p = (size_t)J * L.nx + I;
+    cd o = czero();
+    if (unknown(L, I, J)) {
+        if (I < 2 || J < 2 || I > L.nx - 3 || J > L.ny - 3) {
+            cd ap;
+            double aw, ae, as, an;
+            coef5(L, make_double2(1.0, 0.0), I, J, ap, aw, ae, as, an);
+            o = cmul(ap, u[p]);
+            if (aw != 0.0) caxpy(o, aw, u[p - 1]);
+            if (ae != 0.0) caxpy(o, ae, u[p + 1]);
+            if (as != 0.0) caxpy(o, as, u[p - L.nx]);
+            if (an != 0.0) caxpy(o, an, u[p + L.nx]);
+        } else {
+            const double ax = L.ihx2 / 12.0, ay = L.ihy2 / 12.0;
+            const double k = kat(L, I, J);
+            const cd uc = u[p];
+            // Dirichlet boundary nodes are not unknowns: they read as zero
+            const cd lx = cadd(cadd(uat(L, u, I - 2, J), uat(L, u, I + 2, J)),
+                               cadd(cscal(-16.0, cadd(uat(L, u, I - 1, J), uat(L, u, I + 1, J))),
+                                    cscal(30.0, uc)));
+            const cd ly = cadd(cadd(uat(L, u, I, J - 2), uat(L, u, I, J + 2)),
+                               cadd(cscal(-16.0, cadd(uat(L, u, I, J - 1), uat(L, u, I, J + 1))),
+                                    cscal(30.0, uc)));
+            o = cadd(cadd(cscal(ax, lx), cscal(ay, ly)), cscal(-k * k, uc));
+        }
+        if (RESID) o = csub(b[p], o);
+    }
+    y[p] = o;
+}
+
+hipError_t launch_redo4(const Lev &L, const cd *x, const cd *b, cd *y, hipStream_t st)
+{
+    const int tx = cdiv(L.nx, 64), ty = cdiv(L.ny, 4);
+    if (b)
+        k_redo4<true><<<tx * ty, 256, 0, st>>>(L, x, b, y, tx);
+    else
+        k_redo4<false><<<tx * ty, 256, 0, st>>>(L, x, b, y, tx);
     HD_LAUNCH_CHECK();
 }
 

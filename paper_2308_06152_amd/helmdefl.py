@@ -20,9 +20,10 @@ HELM_ENOMEM, HELM_EHIP, HELM_ENOCONV = -4, -5, -6
 BC_DIRICHLET, BC_SOMMERFELD = 0, 1
 DEFL_Q, DEFL_P, DEFL_ADEF1 = 0, 1, 2
 Z_LINEAR, Z_HIGH = 0, 1
-COARSE_GALERKIN, COARSE_REDGLK2 = 0, 1
+COARSE_GALERKIN, COARSE_REDGLK2, COARSE_REDO2, COARSE_REDO4, COARSE_REDGLK1 = 0, 1, 2, 3, 4
 CMODE_FIXED, CMODE_TOL = 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
+OUTER_FGMRES, OUTER_GCR, OUTER_GMRES_LEFT = 0, 1, 2
 K_APPLY, K_VC_DOWN, K_VC_UP, K_ZT, K_DRESID, K_COARSE, K_DOT, K_UPDATE = range(8)
 KERNEL_CLASS_NAMES = ["apply5", "vc_down", "vc_up", "zt", "dresid", "coarse_op", "mdot",
                       "mupdate"]
@@ -48,7 +49,8 @@ class Opts(ctypes.Structure):
                 ("coarse_restart", ctypes.c_int), ("coarse_tol", ctypes.c_double),
                 ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("tol", ctypes.c_double),
                 ("x0_given", ctypes.c_int), ("force_iters", ctypes.c_int),
-                ("coarsest_nodes", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("coarsest_nodes", ctypes.c_int), ("precision", ctypes.c_int),
+                ("outer", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -48,6 +48,7 @@ def test_defaults_and_strerror(H):
     assert o.defl_vectors == H.Z_HIGH
     assert o.coarsest_nodes == 1089
     assert o.precision == H.PREC_FP64
+    assert o.outer == H.OUTER_FGMRES
     L = H.load()
     assert L.helm_strerror(0) == b"success"
     assert b"coarsen" in L.helm_strerror(H.HELM_EGRID)
@@ -73,7 +74,8 @@ def test_create_rejects_uncoarsenable_grids(H, nx, ny):
                                 dict(coarse_mode=0), dict(coarse_op=7), dict(defl_vectors=3),
                                 dict(omega=0.0), dict(tol=-1.0), dict(coarsest_nodes=-1),
                                 dict(coarsest_nodes=5000), dict(precision=2),
-                                dict(precision=-1)])
+                                dict(precision=-1), dict(coarse_op=5), dict(coarse_op=-1),
+                                dict(outer=3), dict(outer=-1)])
 def test_create_rejects_bad_options(H, kw):
     assert _create(H, 9, 9, **kw) == H.HELM_EINVAL
 
@@ -82,8 +84,9 @@ def test_create_rejects_bad_grid_values(H):
     assert _create(H, 9, 9, hx=0.0) == H.HELM_EINVAL
     assert _create(H, 9, 9, hx=float("nan")) == H.HELM_EINVAL
     assert _create(H, 9, 9, bc=5) == H.HELM_EINVAL
-    # ReD-Glk2 is defined for hx == hy only
+    # ReD-Glk2 and ReD-Glk1 are defined for hx == hy only
     assert _create(H, 9, 9, hx=0.1, hy=0.2, coarse_op=1) == H.HELM_EINVAL
+    assert _create(H, 9, 9, hx=0.1, hy=0.2, coarse_op=4) == H.HELM_EINVAL
     assert _create(H, 9, 9, kconst=float("inf")) == H.HELM_ENONFINITE
     assert _create(H, 9, 9, kconst=-1.0) == H.HELM_ENONFINITE
 
