@@ -110,6 +110,13 @@ typedef struct {
                                 the residual test stay FP64; FGMRES absorbs the
                                 perturbed preconditioner (Section 5.2). */
     int outer;               /* HELM_OUTER_* (default HELM_OUTER_FGMRES)       */
+    int batch;               /* nrhs > 1 with the FP64 path: 1 (default) = all
+                                right-hand sides in one batched pass (one launch
+                                per kernel for all of them; helm_solve runs one
+                                FGMRES per right-hand side in lockstep, masking
+                                converged ones out); 0 = one after another.
+                                GCR, left GMRES and the mixed-precision option
+                                always go one after another. */
 } helm_opts;
 
 /* Per right-hand side result of helm_solve. */

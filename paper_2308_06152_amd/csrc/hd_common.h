@@ -19,6 +19,18 @@ enum { BC_DIR = 0, BC_SOM = 1 };
 constexpr int PSTRIDE = 64;
 constexpr int MAX_RESTART = 60;
 
+// Batched launches (several right-hand sides of one operator).  Grid y is the
+// right-hand side.  A right-hand side's vectors are contiguous and follow each
+// other at the level's node count (or at an explicit stride for Krylov
+// bases); its small device arrays (projections, norms, scales, coefficients)
+// follow each other at SB entries.  act: per right-hand side 1 = active,
+// 0 = skip (nullptr: all active).
+constexpr int SB = 256;
+struct Batch {
+    int B = 1;
+    const int *act = nullptr;
+};
+
 // One grid level as the kernels see it (passed by value).
 struct Lev {
     int nx, ny;
@@ -104,17 +116,18 @@ __host__ __device__ inline bool coef5(const Lev &L, cd s, int i, int j, cd &ap, 
 // ---- launch wrappers (kernels.hip); all return the launch's hipError_t ----
 
 // y = (-Lap - s k^2) x, or y = b - (-Lap - s k^2) x when b != nullptr.
-hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hipStream_t st);
+hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hipStream_t st,
+                         Batch bt = Batch{});
 // rc = FW( r - M (omega D^-1 r) ): pre-smooth from zero, residual, restriction.
 // The right-hand side is rs[0].x * r when rs != nullptr (a lazily normalised
 // Krylov vector).
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
-                          const cd *rs, cd *rc, hipStream_t st);
+                          const cd *rs, cd *rc, hipStream_t st, Batch bt = Batch{});
 // out (+)= x2 + omega D^-1 (r - M x2), x2 = omega D^-1 r + P ec  [+ Z v2];
 // right-hand side scaled by rs[0].x as above.
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
                         const cd *rs, const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
-                        hipStream_t st);
+                        hipStream_t st, Batch bt = Batch{});
 // Mixed-precision V-cycle (complex64 arithmetic and level storage): the top
 // level reads r in FP64 and writes rc in FP32, and its upward pass reads r in
 // FP64, ec in FP32 and writes out in FP64 (adding Z v2 in FP64); levels below
@@ -129,22 +142,25 @@ hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const 
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
                         const cf *ec, cf *out, hipStream_t st);
 // x = Minv r on the coarsest level (dense inverse, n x n, row major).
-hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st);
+hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st,
+                           Batch bt = Batch{});
 hipError_t launch_coarsest(int n, const cf *Minv, const cf *r, cf *x, hipStream_t st);
 // vc = Z^T vf, or vc = b - Z^T vf when b != nullptr.
 hipError_t launch_zt(const Lev &Lf, const Lev &Lc, int zho, const cd *vf, const cd *b, cd *vc,
-                     hipStream_t st);
+                     hipStream_t st, Batch bt = Batch{});
 // vf = Z vc.
-hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf, hipStream_t st);
+hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf, hipStream_t st,
+                    Batch bt = Batch{});
 // t = v - A_h (Z v2).
 hipError_t launch_dresid(const Lev &Lf, const Lev &Lc, int zho, const cd *v, const cd *v2,
-                         cd *t, hipStream_t st);
+                         cd *t, hipStream_t st, Batch bt = Batch{});
 // y = A_2h x (ReD-Glk2, or ReD-Glk1 when glk1) or y = b - A_2h x; interior
 // and boundary band.
 hipError_t launch_redglk2(const Lev &Lc, const cd *x, const cd *b, cd *y, int glk1,
-                          hipStream_t st);
+                          hipStream_t st, Batch bt = Batch{});
 // y = A_2h x (ReD-O4) or y = b - A_2h x.
-hipError_t launch_redo4(const Lev &Lc, const cd *x, const cd *b, cd *y, hipStream_t st);
+hipError_t launch_redo4(const Lev &Lc, const cd *x, const cd *b, cd *y, hipStream_t st,
+                        Batch bt = Batch{});
 
 // ---- Krylov kernels ----
 // Number of partial-sum blocks used for vectors of length n.
@@ -152,25 +168,31 @@ int krylov_blocks(size_t n);
 // part[blk][i] = sum conj(V_i) w over the block, i < m; slot m = |w|^2 if
 // with_norm.  cond != nullptr: second Gram-Schmidt pass, a no-op unless the
 // reorthogonalisation test on cond (projections, then ||w||^2 at [jcond]) fires.
+// Batched: V and w of right-hand side b start vbs / wbs entries after b-1's.
 hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd *part,
-                       int with_norm, const cd *cond, int jcond, hipStream_t st);
+                       int with_norm, const cd *cond, int jcond, hipStream_t st,
+                       Batch bt = Batch{}, size_t vbs = 0, size_t wbs = 0);
 // w -= sum_i c_i sig_i V_i (sig_i = 1 if sig == nullptr); partn[blk] =
 // |w_new|^2 partial if partn != nullptr.
 hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *partn,
-                          const cd *cond, int jcond, const cd *sig, hipStream_t st);
+                          const cd *cond, int jcond, const cd *sig, hipStream_t st,
+                          Batch bt = Batch{}, size_t vbs = 0, size_t wbs = 0);
 // out[i] (=|+=) sum_blk part[blk][i], i < m (mode 0: times sig[i] for
 // i < nsig); mode 2: out[0] = (sqrt(sum re), 0) and sig_out[0] = its
 // reciprocal.  cond: as above; writes zeros when the second pass is skipped.
 hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, const cd *cond,
-                         int jcond, const cd *sig, int nsig, cd *sig_out, hipStream_t st);
+                         int jcond, const cd *sig, int nsig, cd *sig_out, hipStream_t st,
+                         Batch bt = Batch{});
 // v = w / nrm[0].x (v = 0 if the norm is 0).
-hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t st);
+hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t st,
+                        Batch bt = Batch{}, size_t wbs = 0, size_t vbs = 0);
 // out (+)= sum_i y_i V_i.
 hipError_t launch_lincomb(const cd *V, size_t ld, int m, const cd *y, cd *out, size_t n,
-                          int accumulate, hipStream_t st);
+                          int accumulate, hipStream_t st, Batch bt = Batch{}, size_t vbs = 0,
+                          size_t obs = 0);
 // p[0..n) = 0.
 hipError_t launch_zero(cd *p, size_t n, hipStream_t st);
 // out = in with the non-unknown (Dirichlet boundary) entries set to zero.
-hipError_t launch_mask_copy(const Lev &L, const cd *in, cd *out, hipStream_t st);
+hipError_t launch_mask_copy(const Lev &L, const cd *in, cd *out, hipStream_t st, int B = 1);
 
 }  // namespace hd

@@ -103,6 +103,30 @@ struct Givens {
     }
 };
 
+// Workspace of batched solves: B right-hand sides of one operator in
+// lockstep.  Level buffers are [B][n_l]; Krylov bases are stored j-major,
+// [j][B][n], so basis slot j of every right-hand side is one contiguous block
+// (the input of a batched V-cycle or operator) and vector j of right-hand side
+// b sits at (j*B + b)*n.  Small per-right-hand-side device arrays (projections,
+// norms, 1/||u||, least-squares solutions) are SB entries apart.
+constexpr int HB = 2 * PSTRIDE + 1;  // scalars read back per right-hand side
+constexpr int NMASK = 64;            // rotating active-mask buffers
+
+struct BatchWS {
+    int B = 0;
+    cd *lr[MAXLEV] = {}, *lx[MAXLEV] = {};
+    cd *v1 = nullptr, *v2 = nullptr, *tf = nullptr, *f1 = nullptr, *f2 = nullptr;
+    cd *Vc = nullptr, *wc = nullptr, *zc = nullptr;
+    cd *part = nullptr, *partn = nullptr;
+    cd *hbuf = nullptr, *sig = nullptr, *ydev = nullptr;
+    cd *V = nullptr, *Z = nullptr, *w = nullptr, *bm = nullptr;  // outer FGMRES
+    int *dmask = nullptr;  // NMASK device masks of B entries
+    int *hmask = nullptr;  // their pinned staging
+    int next_mask = 0;
+    cd *hpin = nullptr;    // pinned: 2 read-back slots of B x HB, then y staging B x SB
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
 }  // namespace
 
 struct helm_ctx {
@@ -137,6 +161,7 @@ struct helm_ctx {
     int m = 0;
     cd *V = nullptr, *Z = nullptr, *w = nullptr, *bm = nullptr;
     cd *w2 = nullptr, *r = nullptr;  // GCR / left GMRES work vectors
+    BatchWS *bw = nullptr;           // batched solves (allocated on first use)
 
     // kernel timing
     int t_cls = -1, t_lev = -1;
@@ -849,6 +874,550 @@ int solve_left(helm_ctx *h, const cd *b, cd *x, helm_solve_info *info)
 }
 
 // ---------------------------------------------------------------------------
+// Batched solves (B right-hand sides of one operator, in lockstep).  Every
+// right-hand side keeps its own Krylov basis, Hessenberg matrix and
+// convergence test; the kernels of one step run for all of them in one launch
+// each, and right-hand sides that have converged are masked out on the device.
+// ---------------------------------------------------------------------------
+void free_batch(BatchWS *W)
+{
+    if (!W) return;
+    for (int l = 0; l < MAXLEV; l++) {
+        dfree(W->lr[l]);
+        dfree(W->lx[l]);
+    }
+    for (void *p : {(void *)W->v1, (void *)W->v2, (void *)W->tf, (void *)W->f1, (void *)W->f2,
+                    (void *)W->Vc, (void *)W->wc, (void *)W->zc, (void *)W->part,
+                    (void *)W->partn, (void *)W->hbuf, (void *)W->sig, (void *)W->ydev,
+                    (void *)W->V, (void *)W->Z, (void *)W->w, (void *)W->bm, (void *)W->dmask})
+        dfree(p);
+    if (W->hmask) (void)hipHostFree(W->hmask);
+    if (W->hpin) (void)hipHostFree(W->hpin);
+    for (auto e : W->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete W;
+}
+
+// Batch workspace for exactly B right-hand sides (the layouts depend on B);
+// the outer FGMRES bases only when `outer`.
+int ensure_batch(helm_ctx *h, int B, bool outer)
+{
+    if (h->bw && h->bw->B != B) {
+        HCHK(hipStreamSynchronize(h->st));
+        free_batch(h->bw);
+        h->bw = nullptr;
+    }
+    if (!h->bw) {
+        BatchWS *W = new (std::nothrow) BatchWS();
+        if (!W) return HELM_ENOMEM;
+        W->B = B;
+        const size_t nf = h->L[0].n(), nc = h->L[1].n(), b = (size_t)B;
+        int rc = HELM_OK;
+        for (int l = 1; l < h->nlev && !rc; l++) {
+            rc = dalloc(&W->lr[l], b * h->L[l].n());
+            if (!rc) rc = dalloc(&W->lx[l], b * h->L[l].n());
+        }
+        if (!rc) rc = dalloc(&W->v1, b * nc);
+        if (!rc) rc = dalloc(&W->v2, b * nc);
+        if (!rc) rc = dalloc(&W->tf, b * nf);
+        if (!rc && h->o.coarse_op == HELM_COARSE_GALERKIN) rc = dalloc(&W->f1, b * nf);
+        if (!rc && h->o.coarse_op == HELM_COARSE_GALERKIN) rc = dalloc(&W->f2, b * nf);
+        if (!rc) rc = dalloc(&W->Vc, (size_t)(h->mc + 1) * b * nc);
+        if (!rc) rc = dalloc(&W->wc, b * nc);
+        if (!rc) rc = dalloc(&W->zc, b * nc);
+        if (!rc) rc = dalloc(&W->part, b * krylov_blocks(nf) * PSTRIDE);
+        if (!rc) rc = dalloc(&W->partn, b * krylov_blocks(nf) * PSTRIDE);
+        if (!rc) rc = dalloc(&W->hbuf, b * SB);
+        if (!rc) rc = dalloc(&W->sig, b * SB);
+        if (!rc) rc = dalloc(&W->ydev, b * SB);
+        if (!rc) rc = dalloc(&W->dmask, (size_t)NMASK * b);
+        if (!rc && hipHostMalloc((void **)&W->hmask, (size_t)NMASK * b * sizeof(int)) !=
+                       hipSuccess) {
+            W->hmask = nullptr;
+            rc = HELM_ENOMEM;
+        }
+        if (!rc && hipHostMalloc((void **)&W->hpin, (2 * HB + SB) * b * sizeof(cd)) !=
+                       hipSuccess) {
+            W->hpin = nullptr;
+            rc = HELM_ENOMEM;
+        }
+        for (int q = 0; q < 2 && !rc; q++)
+            if (hipEventCreateWithFlags(&W->ev[q], hipEventDisableTiming) != hipSuccess) {
+                W->ev[q] = nullptr;
+                rc = HELM_EHIP;
+            }
+        if (!rc) {
+            // slot 2*PSTRIDE+1 of every right-hand side holds the constant 1
+            std::vector<cd> init(b * SB, make_double2(0.0, 0.0));
+            for (int q = 0; q < B; q++) init[(size_t)q * SB + 2 * PSTRIDE + 1] = make_double2(1.0, 0.0);
+            if (hipMemcpy(W->hbuf, init.data(), init.size() * sizeof(cd), hipMemcpyHostToDevice) !=
+                hipSuccess)
+                rc = HELM_EHIP;
+        }
+        if (rc) {
+            free_batch(W);
+            return rc;
+        }
+        h->bw = W;
+    }
+    BatchWS *W = h->bw;
+    if (outer && !W->V) {
+        const size_t nf = h->L[0].n(), b = (size_t)B;
+        const int m = h->o.restart;
+        int rc;
+        if ((rc = dalloc(&W->V, (size_t)(m + 1) * b * nf)) ||
+            (rc = dalloc(&W->Z, (size_t)m * b * nf)) || (rc = dalloc(&W->w, b * nf)) ||
+            (rc = dalloc(&W->bm, b * nf))) {
+            dfree(W->V);
+            dfree(W->Z);
+            dfree(W->w);
+            dfree(W->bm);
+            W->V = W->Z = W->w = W->bm = nullptr;
+            return rc;
+        }
+    }
+    return HELM_OK;
+}
+
+// Upload an active mask (host flags) into the next rotating device buffer and
+// return it.  Buffers are reused only after NMASK uploads, and the stream is
+// drained before the first reuse, so no buffer changes under a queued kernel.
+const int *upload_mask(helm_ctx *h, const std::vector<char> &act)
+{
+    BatchWS *W = h->bw;
+    if (W->next_mask == NMASK) {
+        if (hipStreamSynchronize(h->st) != hipSuccess) return nullptr;
+        W->next_mask = 0;
+    }
+    const int q = W->next_mask++;
+    int *hm = W->hmask + (size_t)q * W->B;
+    int *dm = W->dmask + (size_t)q * W->B;
+    for (int b = 0; b < W->B; b++) hm[b] = act[b] ? 1 : 0;
+    if (hipMemcpyAsync(dm, hm, W->B * sizeof(int), hipMemcpyHostToDevice, h->st) != hipSuccess)
+        return nullptr;
+    return dm;
+}
+
+#define MCHK(ptr)                                \
+    do {                                         \
+        if (!(ptr)) return HELM_EHIP;            \
+    } while (0)
+
+// Norms of B vectors (length n each, contiguous) for the active ones; when
+// sig_out is given its entry 0 per right-hand side receives 1/||v||.
+int vnorm_b(helm_ctx *h, const cd *v, size_t n, std::vector<double> &out, cd *sig_out,
+            const int *dm)
+{
+    BatchWS *W = h->bw;
+    const Batch bt{W->B, dm};
+    const int nb = krylov_blocks(n);
+    HCHK(launch_mdot(nullptr, 0, 0, v, n, W->part, 1, nullptr, 0, h->st, bt, 0, n));
+    HCHK(launch_reduce(W->part, nb, 1, W->hbuf + 2 * PSTRIDE, 2, nullptr, 0, nullptr, 0, sig_out,
+                       h->st, bt));
+    HCHK(hipMemcpy2DAsync(W->hpin, sizeof(cd), W->hbuf + 2 * PSTRIDE, SB * sizeof(cd), sizeof(cd),
+                          W->B, hipMemcpyDeviceToHost, h->st));
+    HCHK(hipStreamSynchronize(h->st));
+    out.resize(W->B);
+    for (int b = 0; b < W->B; b++) out[b] = W->hpin[b].x;
+    return HELM_OK;
+}
+
+// Batched V-cycle from level l0 (see vcycle); r, z: B contiguous vectors of
+// level l0; rs: per-right-hand-side scale (SB apart) or nullptr.
+int vcycle_b(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2,
+             const cd *rs, const int *dm)
+{
+    BatchWS *W = h->bw;
+    const Batch bt{W->B, dm};
+    const int Lc = h->nlev - 1;
+    if (l0 == Lc) {
+        const size_t n = h->L[Lc].n();
+        if (!accumulate && !rs) {
+            HCHK(launch_coarsest(h->ncoarsest, h->cinv, r, z, h->st, bt));
+            return HELM_OK;
+        }
+        HCHK(launch_coarsest(h->ncoarsest, h->cinv, r, W->lx[Lc], h->st, bt));
+        HCHK(launch_lincomb(W->lx[Lc], 0, 1, rs ? rs : W->hbuf + 2 * PSTRIDE + 1, z, n, accumulate,
+                            h->st, bt, n, n));
+        return HELM_OK;
+    }
+    const cd *rin = r;
+    for (int l = l0; l < Lc; l++) {
+        HCHK(launch_vc_down(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, rin,
+                            l == l0 ? rs : nullptr, W->lr[l + 1], h->st, bt));
+        rin = W->lr[l + 1];
+    }
+    HCHK(launch_coarsest(h->ncoarsest, h->cinv, W->lr[Lc], W->lx[Lc], h->st, bt));
+    for (int l = Lc - 1; l >= l0; l--) {
+        const bool top = l == l0;
+        HCHK(launch_vc_up(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, top ? r : W->lr[l],
+                          top ? rs : nullptr, W->lx[l + 1], top ? z : W->lx[l],
+                          top ? accumulate : 0, top ? v2 : nullptr, h->zho, h->st, bt));
+    }
+    return HELM_OK;
+}
+
+// y = A_2h x or b - A_2h x for B coarse vectors.
+int coarse_apply_b(helm_ctx *h, const cd *x, const cd *b, cd *y, const int *dm)
+{
+    BatchWS *W = h->bw;
+    const Batch bt{W->B, dm};
+    const Lev Lf = h->lev(0), Lc = h->lev(1);
+    switch (h->o.coarse_op) {
+    case HELM_COARSE_REDGLK2: HCHK(launch_redglk2(Lc, x, b, y, 0, h->st, bt)); break;
+    case HELM_COARSE_REDGLK1: HCHK(launch_redglk2(Lc, x, b, y, 1, h->st, bt)); break;
+    case HELM_COARSE_REDO4: HCHK(launch_redo4(Lc, x, b, y, h->st, bt)); break;
+    case HELM_COARSE_REDO2: HCHK(launch_apply5(Lc, make_double2(1.0, 0.0), x, b, y, h->st, bt)); break;
+    default:
+        HCHK(launch_z(Lf, Lc, h->zho, x, W->f1, h->st, bt));
+        HCHK(launch_apply5(Lf, make_double2(1.0, 0.0), W->f1, nullptr, W->f2, h->st, bt));
+        HCHK(launch_zt(Lf, Lc, h->zho, W->f2, b, y, h->st, bt));
+    }
+    return HELM_OK;
+}
+
+// Lazily normalised Arnoldi step of the batched inner GMRES (as
+// arnoldi_lazy_enqueue, for every active right-hand side): basis slot j1
+// already holds A z; projections and the norm go to read-back slot `slot`.
+int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm)
+{
+    BatchWS *W = h->bw;
+    const Batch bt{W->B, dm};
+    const size_t n = h->L[1].n(), ld = (size_t)W->B * n;
+    const int nb = krylov_blocks(n);
+    cd *w = W->Vc + (size_t)j1 * ld;
+    cd *h1 = W->hbuf, *h2 = W->hbuf + PSTRIDE, *nr = W->hbuf + 2 * PSTRIDE;
+    HCHK(launch_mdot(W->Vc, ld, j1, w, n, W->part, 1, nullptr, 0, h->st, bt, n, n));
+    HCHK(launch_reduce(W->part, nb, j1 + 1, h1, 0, nullptr, 0, W->sig, j1, nullptr, h->st, bt));
+    HCHK(launch_mupdate(w, W->Vc, ld, j1, h1, n, W->partn, nullptr, 0, W->sig, h->st, bt, n, n));
+    HCHK(launch_mdot(W->Vc, ld, j1, w, n, W->part, 0, h1, j1, h->st, bt, n, n));
+    HCHK(launch_reduce(W->part, nb, j1, h2, 0, h1, j1, W->sig, j1, nullptr, h->st, bt));
+    HCHK(launch_mupdate(w, W->Vc, ld, j1, h2, n, W->partn, h1, j1, W->sig, h->st, bt, n, n));
+    HCHK(launch_reduce(W->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, W->sig + j1, h->st, bt));
+    HCHK(hipMemcpy2DAsync(W->hpin + (size_t)slot * HB * W->B, HB * sizeof(cd), W->hbuf,
+                          SB * sizeof(cd), HB * sizeof(cd), W->B, hipMemcpyDeviceToHost, h->st));
+    HCHK(hipEventRecord(W->ev[slot], h->st));
+    return HELM_OK;
+}
+
+// Projections (both passes summed) and norm of right-hand side b from a
+// read-back slot.
+double read_col(const BatchWS *W, int slot, int b, int j1, zc *col)
+{
+    const cd *hp = W->hpin + ((size_t)slot * W->B + b) * HB;
+    for (int i = 0; i < j1; i++)
+        col[i] = zc(hp[i].x + hp[PSTRIDE + i].x, hp[i].y + hp[PSTRIDE + i].y);
+    return hp[2 * PSTRIDE].x;
+}
+
+int inner_step_b(helm_ctx *h, int j, int slot, const int *dm)
+{
+    BatchWS *W = h->bw;
+    const size_t ld = (size_t)W->B * h->L[1].n();
+    RCHK(vcycle_b(h, 1, W->Vc + (size_t)j * ld, W->zc, 0, nullptr, W->sig + j, dm));
+    RCHK(coarse_apply_b(h, W->zc, nullptr, W->Vc + (size_t)(j + 1) * ld, dm));
+    return arnoldi_lazy_b(h, j + 1, slot, dm);
+}
+
+// Upload per-right-hand-side least-squares solutions (y[b], zero-padded to
+// jmax) into W->ydev.
+int upload_y_b(helm_ctx *h, const std::vector<std::vector<zc>> &y, int jmax)
+{
+    BatchWS *W = h->bw;
+    cd *stg = W->hpin + (size_t)2 * HB * W->B;
+    for (int b = 0; b < W->B; b++)
+        for (int i = 0; i < jmax; i++) {
+            const zc v = i < (int)y[b].size() ? y[b][i] : zc(0);
+            stg[(size_t)b * SB + i] = make_double2(v.real(), v.imag());
+        }
+    HCHK(hipMemcpyAsync(W->ydev, stg, (size_t)W->B * SB * sizeof(cd), hipMemcpyHostToDevice,
+                        h->st));
+    HCHK(hipStreamSynchronize(h->st));  // the staging buffer is reused next time
+    return HELM_OK;
+}
+
+// Batched coarse solve (coarse_solve for every right-hand side with
+// act[b]): b, x are B contiguous coarse vectors.  Each right-hand side runs
+// its own restarted GMRES; all active ones step together and those that meet
+// their tolerance leave the active mask.  iters[b] receives the counts.
+int coarse_solve_b(helm_ctx *h, const cd *bvec, cd *x, const std::vector<char> &act,
+                   std::vector<int> &iters)
+{
+    BatchWS *W = h->bw;
+    const int B = W->B;
+    const size_t n = h->L[1].n(), ld = (size_t)B * n;
+    const int m = h->mc;
+    const bool fixed = h->o.coarse_mode == HELM_CMODE_FIXED;
+    const int cap = h->o.coarse_iters;
+    const double tol = h->o.coarse_tol;
+    iters.assign(B, 0);
+    std::vector<char> live(act);
+    const int *dm = upload_mask(h, live);
+    MCHK(dm);
+    std::vector<double> bn, beta;
+    RCHK(vnorm_b(h, bvec, n, bn, W->sig, dm));
+    HCHK(launch_zero(x, (size_t)B * n, h->st));
+    for (int b = 0; b < B; b++) {
+        if (!live[b]) continue;
+        if (!std::isfinite(bn[b])) return HELM_ENONFINITE;
+        if (bn[b] == 0.0) live[b] = 0;
+    }
+    std::vector<Givens> gv(B, Givens(m));
+    std::vector<std::vector<double>> unorm(B, std::vector<double>(m + 1));
+    std::vector<std::vector<zc>> y(B);
+    std::vector<int> jend(B);
+    std::vector<char> stop(B), cyc(B), stepm(B);
+    std::vector<zc> col(m + 1);
+    bool first = true;
+    for (;;) {
+        if (first) {
+            HCHK(hipMemcpyAsync(W->Vc, bvec, ld * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
+            beta = bn;  // sig[.][0] = 1/||b|| was stored by vnorm_b
+        } else {
+            dm = upload_mask(h, live);
+            MCHK(dm);
+            RCHK(coarse_apply_b(h, x, bvec, W->Vc, dm));
+            RCHK(vnorm_b(h, W->Vc, n, beta, W->sig, dm));
+            for (int b = 0; b < B; b++)
+                if (live[b] && ((!fixed && beta[b] <= tol * bn[b]) || beta[b] == 0.0)) live[b] = 0;
+        }
+        int nlive = 0, itmin = cap;
+        for (int b = 0; b < B; b++)
+            if (live[b] && iters[b] < cap) {
+                nlive++;
+                itmin = std::min(itmin, iters[b]);
+            } else {
+                live[b] = 0;
+            }
+        if (nlive == 0) break;
+        cyc = live;
+        stepm = live;
+        dm = upload_mask(h, stepm);
+        MCHK(dm);
+        for (int b = 0; b < B; b++) {
+            stop[b] = 0;
+            jend[b] = 0;
+            if (!cyc[b]) continue;
+            gv[b].start(beta[b]);
+            unorm[b][0] = beta[b];
+        }
+        const int steps = std::min(m, cap - itmin);
+        RCHK(inner_step_b(h, 0, 0, dm));
+        for (int j = 0; j < steps; j++) {
+            if (j + 1 < steps) RCHK(inner_step_b(h, j + 1, (j + 1) & 1, dm));
+            HCHK(hipEventSynchronize(W->ev[j & 1]));
+            bool changed = false;
+            int nstep = 0;
+            for (int b = 0; b < B; b++) {
+                if (!stepm[b]) continue;
+                const double hn = read_col(W, j & 1, b, j + 1, col.data());
+                const double res = gv[b].add_column(j, col.data(), hn);
+                iters[b]++;
+                jend[b] = j + 1;
+                unorm[b][j + 1] = hn;
+                if ((!fixed && res <= tol * bn[b]) || hn == 0.0 || iters[b] >= cap) {
+                    stop[b] = 1;
+                    stepm[b] = 0;
+                    changed = true;
+                } else {
+                    nstep++;
+                }
+            }
+            if (nstep == 0) break;
+            if (changed) {
+                dm = upload_mask(h, stepm);
+                MCHK(dm);
+            }
+        }
+        // x += V-cycle(sum_i y_i v_i) for every right-hand side of the cycle
+        int jmax = 0;
+        for (int b = 0; b < B; b++) {
+            y[b].clear();
+            if (!cyc[b]) continue;
+            gv[b].solve(jend[b], y[b]);
+            for (int i = 0; i < jend[b]; i++) y[b][i] /= unorm[b][i];
+            jmax = std::max(jmax, jend[b]);
+        }
+        RCHK(upload_y_b(h, y, jmax));
+        dm = upload_mask(h, cyc);
+        MCHK(dm);
+        HCHK(launch_lincomb(W->Vc, ld, jmax, W->ydev, W->wc, n, 0, h->st, Batch{B, dm}, n, n));
+        RCHK(vcycle_b(h, 1, W->wc, x, 1, nullptr, nullptr, dm));
+        for (int b = 0; b < B; b++)
+            if (cyc[b] && ((fixed && stop[b]) || iters[b] >= cap)) live[b] = 0;
+        first = false;
+    }
+    return HELM_OK;
+}
+
+// Batched A-DEF1 (or Q, P) applied to B fine vectors v -> w for act[b].
+int deflate_b(helm_ctx *h, int mode, const cd *v, cd *w, const std::vector<char> &act,
+              std::vector<int> &inner)
+{
+    BatchWS *W = h->bw;
+    const Lev Lf = h->lev(0), Lc = h->lev(1);
+    const int *dm = upload_mask(h, act);
+    MCHK(dm);
+    const Batch bt{W->B, dm};
+    HCHK(launch_zt(Lf, Lc, h->zho, v, nullptr, W->v1, h->st, bt));
+    RCHK(coarse_solve_b(h, W->v1, W->v2, act, inner));
+    dm = upload_mask(h, act);
+    MCHK(dm);
+    const Batch bt2{W->B, dm};
+    if (mode == HELM_DEFL_Q) {
+        HCHK(launch_z(Lf, Lc, h->zho, W->v2, w, h->st, bt2));
+        return HELM_OK;
+    }
+    cd *t = mode == HELM_DEFL_P ? w : W->tf;
+    HCHK(launch_dresid(Lf, Lc, h->zho, v, W->v2, t, h->st, bt2));
+    if (mode == HELM_DEFL_P) return HELM_OK;
+    return vcycle_b(h, 0, W->tf, w, 0, W->v2, nullptr, dm);
+}
+
+// Arnoldi step of the batched outer FGMRES (as arnoldi_step): W->w holds
+// A z_j of every right-hand side; V is [m+1][B][n].
+int arnoldi_b(helm_ctx *h, int j1, const int *dm)
+{
+    BatchWS *W = h->bw;
+    const Batch bt{W->B, dm};
+    const size_t n = h->L[0].n(), ld = (size_t)W->B * n;
+    const int nb = krylov_blocks(n);
+    cd *h1 = W->hbuf, *h2 = W->hbuf + PSTRIDE, *nr = W->hbuf + 2 * PSTRIDE;
+    HCHK(launch_mdot(W->V, ld, j1, W->w, n, W->part, 1, nullptr, 0, h->st, bt, n, n));
+    HCHK(launch_reduce(W->part, nb, j1 + 1, h1, 0, nullptr, 0, nullptr, 0, nullptr, h->st, bt));
+    HCHK(launch_mupdate(W->w, W->V, ld, j1, h1, n, W->partn, nullptr, 0, nullptr, h->st, bt, n,
+                        n));
+    HCHK(launch_mdot(W->V, ld, j1, W->w, n, W->part, 0, h1, j1, h->st, bt, n, n));
+    HCHK(launch_reduce(W->part, nb, j1, h2, 0, h1, j1, nullptr, 0, nullptr, h->st, bt));
+    HCHK(launch_mupdate(W->w, W->V, ld, j1, h2, n, W->partn, h1, j1, nullptr, h->st, bt, n, n));
+    HCHK(launch_reduce(W->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, nullptr, h->st, bt));
+    HCHK(launch_scale(W->w, nr, W->V + (size_t)j1 * ld, n, h->st, bt, n, n));
+    HCHK(hipMemcpy2DAsync(W->hpin, HB * sizeof(cd), W->hbuf, SB * sizeof(cd), HB * sizeof(cd),
+                          W->B, hipMemcpyDeviceToHost, h->st));
+    HCHK(hipStreamSynchronize(h->st));
+    return HELM_OK;
+}
+
+// Flexible GMRES(m) for B right-hand sides of one operator in lockstep (as
+// solve_one for each): b, x are [B][ny][nx].
+int solve_b(helm_ctx *h, const cd *b, cd *x, int B, helm_solve_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    RCHK(ensure_batch(h, B, true));
+    BatchWS *W = h->bw;
+    const size_t n = h->L[0].n(), ld = (size_t)B * n;
+    const int m = h->o.restart;
+    const Lev L0 = h->lev(0);
+    const int force = h->o.force_iters;
+    const int cap = force > 0 ? force : h->o.maxit;
+    std::vector<helm_solve_info> inf(B);
+    HCHK(launch_mask_copy(L0, b, W->bm, h->st, B));
+    std::vector<char> all(B, 1);
+    const int *dm = upload_mask(h, all);
+    MCHK(dm);
+    std::vector<double> bn, beta;
+    RCHK(vnorm_b(h, W->bm, n, bn, nullptr, dm));
+    for (int q = 0; q < B; q++)
+        if (!std::isfinite(bn[q])) return HELM_ENONFINITE;
+    if (h->o.x0_given)
+        HCHK(launch_mask_copy(L0, x, x, h->st, B));
+    else
+        HCHK(launch_zero(x, ld, h->st));
+    std::vector<char> live(B), cyc(B), stepm(B);
+    for (int q = 0; q < B; q++) {
+        live[q] = bn[q] > 0.0;
+        if (!live[q]) inf[q].converged = 1;
+    }
+    std::vector<Givens> gv(B, Givens(m));
+    std::vector<std::vector<zc>> y(B);
+    std::vector<int> jend(B), inner;
+    std::vector<zc> col(m + 1);
+    for (;;) {
+        // true residual of every live right-hand side
+        dm = upload_mask(h, live);
+        MCHK(dm);
+        HCHK(launch_apply5(L0, make_double2(1.0, 0.0), x, W->bm, W->w, h->st, Batch{B, dm}));
+        RCHK(vnorm_b(h, W->w, n, beta, nullptr, dm));
+        int nlive = 0;
+        for (int q = 0; q < B; q++) {
+            if (!live[q]) continue;
+            inf[q].relres = beta[q] / bn[q];
+            if (force > 0 && inf[q].outer_iters >= cap) {
+                inf[q].converged = inf[q].relres <= h->o.tol;
+                live[q] = 0;
+            } else if (force <= 0 && inf[q].relres <= h->o.tol) {
+                inf[q].converged = 1;
+                live[q] = 0;
+            } else if (inf[q].outer_iters >= cap || beta[q] == 0.0) {
+                live[q] = 0;
+            } else {
+                nlive++;
+            }
+        }
+        if (nlive == 0) break;
+        cyc = live;
+        stepm = live;
+        dm = upload_mask(h, stepm);
+        MCHK(dm);
+        // v_0 = r / ||r|| (the norms sit in hbuf[2*PSTRIDE] of each right-hand side)
+        HCHK(launch_scale(W->w, W->hbuf + 2 * PSTRIDE, W->V, n, h->st, Batch{B, dm}, n, n));
+        for (int q = 0; q < B; q++) {
+            jend[q] = 0;
+            if (cyc[q]) gv[q].start(beta[q]);
+        }
+        for (int j = 0; j < m; j++) {
+            RCHK(deflate_b(h, HELM_DEFL_ADEF1, W->V + (size_t)j * ld, W->Z + (size_t)j * ld,
+                           stepm, inner));
+            dm = upload_mask(h, stepm);
+            MCHK(dm);
+            HCHK(launch_apply5(L0, make_double2(1.0, 0.0), W->Z + (size_t)j * ld, nullptr, W->w,
+                               h->st, Batch{B, dm}));
+            RCHK(arnoldi_b(h, j + 1, dm));
+            int nstep = 0;
+            for (int q = 0; q < B; q++) {
+                if (!stepm[q]) continue;
+                const double hn = read_col(W, 0, q, j + 1, col.data());
+                const double res = gv[q].add_column(j, col.data(), hn);
+                inf[q].outer_iters++;
+                inf[q].inner_iters_total += inner[q];
+                inf[q].inner_iters_max = std::max(inf[q].inner_iters_max, inner[q]);
+                jend[q] = j + 1;
+                if ((force <= 0 && res <= h->o.tol * bn[q]) || hn == 0.0 ||
+                    inf[q].outer_iters >= cap)
+                    stepm[q] = 0;
+                else
+                    nstep++;
+            }
+            if (std::getenv("HELMDEFL_LOG"))
+                std::fprintf(stderr, "helmdefl: batch outer step %d, %d right-hand sides active\n",
+                             j + 1, nstep);
+            if (nstep == 0) break;
+        }
+        int jmax = 0;
+        for (int q = 0; q < B; q++) {
+            y[q].clear();
+            if (!cyc[q]) continue;
+            gv[q].solve(jend[q], y[q]);
+            jmax = std::max(jmax, jend[q]);
+        }
+        RCHK(upload_y_b(h, y, jmax));
+        dm = upload_mask(h, cyc);
+        MCHK(dm);
+        HCHK(launch_lincomb(W->Z, ld, jmax, W->ydev, x, n, 1, h->st, Batch{B, dm}, n, n));
+    }
+    HCHK(hipStreamSynchronize(h->st));
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int rc = HELM_OK;
+    for (int q = 0; q < B; q++) {
+        inf[q].t_solve_ms = ms;
+        if (!inf[q].converged && force <= 0) rc = HELM_ENOCONV;
+        if (info) info[q] = inf[q];
+    }
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
 
@@ -968,6 +1537,7 @@ void release(helm_ctx *h)
         (void)hipEventDestroy(p.b);
     }
     for (auto e : h->ev_free) (void)hipEventDestroy(e);
+    free_batch(h->bw);
     delete h;
 }
 
@@ -992,6 +1562,7 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
         g->hx != g->hy)
         return HELM_EINVAL;
     if (o.outer < HELM_OUTER_FGMRES || o.outer > HELM_OUTER_GMRES_LEFT) return HELM_EINVAL;
+    if (o.batch != 0 && o.batch != 1) return HELM_EINVAL;
     if (o.coarse_mode != HELM_CMODE_FIXED && o.coarse_mode != HELM_CMODE_TOL) return HELM_EINVAL;
     if (o.coarse_iters < 1 || o.coarse_restart < 1 || o.coarse_restart > MAX_RESTART)
         return HELM_EINVAL;
@@ -1138,6 +1709,7 @@ int helm_opts_default(helm_opts *o)
     o->coarsest_nodes = 1089;
     o->precision = HELM_PREC_FP64;
     o->outer = HELM_OUTER_FGMRES;
+    o->batch = 1;
     return HELM_OK;
 }
 
@@ -1161,18 +1733,36 @@ int helm_destroy(helm_ctx *h)
 int helm_apply(helm_ctx *h, const void *x, void *y, int nrhs)
 {
     if (!valid(h) || !x || !y || nrhs < 1) return HELM_EINVAL;
-    const size_t n = h->L[0].n();
-    for (int r = 0; r < nrhs; r++)
-        RCHK(apply_A(h, 0, (const cd *)x + r * n, nullptr, (cd *)y + r * n));
-    return HELM_OK;
+    if (nrhs > 1) {
+        // one launch for all right-hand sides
+        HCHK(launch_apply5(h->lev(0), make_double2(1.0, 0.0), (const cd *)x, nullptr, (cd *)y,
+                           h->st, Batch{nrhs, nullptr}));
+        return HELM_OK;
+    }
+    return apply_A(h, 0, (const cd *)x, nullptr, (cd *)y);
+}
+
+// Several right-hand sides go through the batched kernels when the option
+// asks for it and the FP64 path is in use.
+static bool batched(const helm_ctx *h, int nrhs)
+{
+    return nrhs > 1 && h->o.batch && h->o.precision == HELM_PREC_FP64;
 }
 
 int cslp_vcycle(helm_ctx *h, const void *r, void *z, int nrhs)
 {
     if (!valid(h) || !r || !z || nrhs < 1) return HELM_EINVAL;
     const size_t n = h->L[0].n();
-    for (int q = 0; q < nrhs; q++)
-        RCHK(vcycle(h, 0, (const cd *)r + q * n, (cd *)z + q * n, 0, nullptr));
+    try {
+        if (batched(h, nrhs)) {
+            RCHK(ensure_batch(h, nrhs, false));
+            return vcycle_b(h, 0, (const cd *)r, (cd *)z, 0, nullptr, nullptr, nullptr);
+        }
+        for (int q = 0; q < nrhs; q++)
+            RCHK(vcycle(h, 0, (const cd *)r + q * n, (cd *)z + q * n, 0, nullptr));
+    } catch (...) {
+        return HELM_ENOMEM;
+    }
     return HELM_OK;
 }
 
@@ -1182,6 +1772,12 @@ int deflate_apply(helm_ctx *h, int mode, const void *v, void *w, int nrhs)
     if (mode != HELM_DEFL_Q && mode != HELM_DEFL_P && mode != HELM_DEFL_ADEF1) return HELM_EINVAL;
     const size_t n = h->L[0].n();
     try {
+        if (batched(h, nrhs)) {
+            RCHK(ensure_batch(h, nrhs, false));
+            std::vector<char> all(nrhs, 1);
+            std::vector<int> inner;
+            return deflate_b(h, mode, (const cd *)v, (cd *)w, all, inner);
+        }
         for (int q = 0; q < nrhs; q++)
             RCHK(deflate_one(h, mode, (const cd *)v + q * n, (cd *)w + q * n, nullptr));
     } catch (...) {
@@ -1196,6 +1792,8 @@ int helm_solve(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *i
     const size_t n = h->L[0].n();
     int worst = HELM_OK;
     try {
+        if (batched(h, nrhs) && h->o.outer == HELM_OUTER_FGMRES)
+            return solve_b(h, (const cd *)b, (cd *)x, nrhs, info);
         RCHK(ensure_outer(h));
         for (int q = 0; q < nrhs; q++) {
             const cd *bq = (const cd *)b + q * n;

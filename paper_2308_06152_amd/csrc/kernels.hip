@@ -81,6 +81,10 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
 
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// Batched launches: blockIdx.y is the right-hand side; a block of an inactive
+// right-hand side exits at once.
+__device__ __forceinline__ bool skip_rhs(const Batch &bt) { return bt.act && !bt.act[blockIdx.y]; }
+
 // 1D interpolation rule from the coarse grid to fine index i: returns the
 // number of coarse neighbours and fills their indices and weights.
 // zho = 1: Bezier vectors (even i: (1, 6, 1)/8 on I-1, I, I+1; odd: 1/2, 1/2);
@@ -139,8 +143,15 @@ constexpr int AP_TX = 64, AP_TY = 16, AP_RPT = 4;
 template <bool RESID>
 __global__ __launch_bounds__(256) void k_apply5(Lev L, cd s, const cd *__restrict__ x,
                                                 const cd *__restrict__ b, cd *__restrict__ y,
-                                                int tiles_x)
+                                                int tiles_x, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    {
+        const size_t off = (size_t)blockIdx.y * L.nx * L.ny;
+        x += off;
+        if (RESID) b += off;
+        y += off;
+    }
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i = (t % tiles_x) * AP_TX + (threadIdx.x & 63);
     const int j0 = (t / tiles_x) * AP_TY + (threadIdx.x >> 6) * AP_RPT;
@@ -171,13 +182,15 @@ __global__ __launch_bounds__(256) void k_apply5(Lev L, cd s, const cd *__restric
     }
 }
 
-hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hipStream_t st)
+hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hipStream_t st,
+                         Batch bt)
 {
     const int tx = cdiv(L.nx, AP_TX), ty = cdiv(L.ny, AP_TY);
+    const dim3 g(tx * ty, bt.B);
     if (b)
-        k_apply5<true><<<tx * ty, 256, 0, st>>>(L, s, x, b, y, tx);
+        k_apply5<true><<<g, 256, 0, st>>>(L, s, x, b, y, tx, bt);
     else
-        k_apply5<false><<<tx * ty, 256, 0, st>>>(L, s, x, b, y, tx);
+        k_apply5<false><<<g, 256, 0, st>>>(L, s, x, b, y, tx, bt);
     HD_LAUNCH_CHECK();
 }
 
@@ -263,8 +276,12 @@ template <bool VARK, class RI, class R>
 __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double omega,
                                                  Smooth<R> c, const cx<RI> *__restrict__ r,
                                                  const cd *__restrict__ rs,
-                                                 cx<R> *__restrict__ rc, int tiles_x)
+                                                 cx<R> *__restrict__ rc, int tiles_x, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    r += (size_t)blockIdx.y * Lf.nx * Lf.ny;
+    rc += (size_t)blockIdx.y * Lc.nx * Lc.ny;
+    if (rs) rs += (size_t)blockIdx.y * SB;
     // Thread (cx, cy) computes coarse node (I0+cx, J0+cy) and owns the 2 x 2
     // fine nodes (2I+dx, 2J+dy), keeping r and then r1 there in registers.
     // One LDS tile (67 x 19, local (a, b) = fine (2*I0-2+a, 2*J0-2+b)) holds
@@ -365,33 +382,34 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
 
 template <class RI, class R>
 static hipError_t vc_down_t(const Lev &Lf, const Lev &Lc, cd s, double omega, const cx<RI> *r,
-                            const cd *rs, cx<R> *rc, hipStream_t st)
+                            const cd *rs, cx<R> *rc, hipStream_t st, Batch bt)
 {
     const int tx = cdiv(Lc.nx, VD_CX), ty = cdiv(Lc.ny, VD_CY);
     const Smooth<R> c = smooth_consts<R>(Lf, s, omega);
+    const dim3 g(tx * ty, bt.B);
     if (Lf.k)
-        k_vc_down<true, RI, R><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx);
+        k_vc_down<true, RI, R><<<g, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx, bt);
     else
-        k_vc_down<false, RI, R><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx);
+        k_vc_down<false, RI, R><<<g, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, rc, tx, bt);
     HD_LAUNCH_CHECK();
 }
 
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
-                          const cd *rs, cd *rc, hipStream_t st)
+                          const cd *rs, cd *rc, hipStream_t st, Batch bt)
 {
-    return vc_down_t<double, double>(Lf, Lc, s, omega, r, rs, rc, st);
+    return vc_down_t<double, double>(Lf, Lc, s, omega, r, rs, rc, st, bt);
 }
 
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r, cf *rc,
                           hipStream_t st)
 {
-    return vc_down_t<double, float>(Lf, Lc, s, omega, r, nullptr, rc, st);
+    return vc_down_t<double, float>(Lf, Lc, s, omega, r, nullptr, rc, st, Batch{});
 }
 
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r, cf *rc,
                           hipStream_t st)
 {
-    return vc_down_t<float, float>(Lf, Lc, s, omega, r, nullptr, rc, st);
+    return vc_down_t<float, float>(Lf, Lc, s, omega, r, nullptr, rc, st, Batch{});
 }
 
 // ------------------------------------------------------------------------
@@ -416,8 +434,18 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
                                                const cd *__restrict__ rs,
                                                const cx<R> *__restrict__ ec,
                                                cx<RO> *__restrict__ out, int accumulate,
-                                               const cd *__restrict__ v2, int zho, int tiles_x)
+                                               const cd *__restrict__ v2, int zho, int tiles_x,
+                                               Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    {
+        const size_t nf = (size_t)Lf.nx * Lf.ny, nc = (size_t)Lc.nx * Lc.ny;
+        r += blockIdx.y * nf;
+        out += blockIdx.y * nf;
+        ec += blockIdx.y * nc;
+        if (v2) v2 += blockIdx.y * nc;
+        if (rs) rs += (size_t)blockIdx.y * SB;
+    }
     // Thread (tx, ty) owns output column tx and rows 4*ty .. 4*ty+3 of the
     // 64 x 16 tile and keeps r there in registers; x2 (66 x 18 with its
     // one-node halo) and the coarse correction tile (34 x 10) live in LDS.
@@ -535,25 +563,26 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
 template <class RI, class R, class RO>
 static hipError_t vc_up_t(const Lev &Lf, const Lev &Lc, cd s, double omega, const cx<RI> *r,
                           const cd *rs, const cx<R> *ec, cx<RO> *out, int accumulate,
-                          const cd *v2, int zho, hipStream_t st)
+                          const cd *v2, int zho, hipStream_t st, Batch bt)
 {
     const int tx = cdiv(Lf.nx, VU_TX), ty = cdiv(Lf.ny, VU_TY);
     const Smooth<R> c = smooth_consts<R>(Lf, s, omega);
+    const dim3 g(tx * ty, bt.B);
     if (Lf.k)
-        k_vc_up<true, RI, R, RO><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out,
-                                                          accumulate, v2, zho, tx);
+        k_vc_up<true, RI, R, RO><<<g, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out,
+                                                    accumulate, v2, zho, tx, bt);
     else
-        k_vc_up<false, RI, R, RO><<<tx * ty, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out,
-                                                           accumulate, v2, zho, tx);
+        k_vc_up<false, RI, R, RO><<<g, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out,
+                                                     accumulate, v2, zho, tx, bt);
     HD_LAUNCH_CHECK();
 }
 
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
                         const cd *rs, const cd *ec, cd *out, int accumulate, const cd *v2, int zho,
-                        hipStream_t st)
+                        hipStream_t st, Batch bt)
 {
     return vc_up_t<double, double, double>(Lf, Lc, s, omega, r, rs, ec, out, accumulate, v2, zho,
-                                           st);
+                                           st, bt);
 }
 
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
@@ -561,13 +590,14 @@ hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const 
                         hipStream_t st)
 {
     return vc_up_t<double, float, double>(Lf, Lc, s, omega, r, nullptr, ec, out, accumulate, v2,
-                                          zho, st);
+                                          zho, st, Batch{});
 }
 
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
                         const cf *ec, cf *out, hipStream_t st)
 {
-    return vc_up_t<float, float, float>(Lf, Lc, s, omega, r, nullptr, ec, out, 0, nullptr, 0, st);
+    return vc_up_t<float, float, float>(Lf, Lc, s, omega, r, nullptr, ec, out, 0, nullptr, 0, st,
+                                        Batch{});
 }
 
 // ------------------------------------------------------------------------
@@ -592,8 +622,11 @@ __device__ __forceinline__ cx<R> wave_sum64(cx<R> v)
 template <class R>
 __global__ __launch_bounds__(256) void k_coarsest(int n, const cx<R> *__restrict__ Minv,
                                                   const cx<R> *__restrict__ r,
-                                                  cx<R> *__restrict__ x)
+                                                  cx<R> *__restrict__ x, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    r += (size_t)blockIdx.y * n;
+    x += (size_t)blockIdx.y * n;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n) return;
@@ -611,15 +644,15 @@ __global__ __launch_bounds__(256) void k_coarsest(int n, const cx<R> *__restrict
     if (lane == 0) x[row] = s;
 }
 
-hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st)
+hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st, Batch bt)
 {
-    k_coarsest<double><<<cdiv(n, 4), 256, 0, st>>>(n, Minv, r, x);
+    k_coarsest<double><<<dim3(cdiv(n, 4), bt.B), 256, 0, st>>>(n, Minv, r, x, bt);
     HD_LAUNCH_CHECK();
 }
 
 hipError_t launch_coarsest(int n, const cf *Minv, const cf *r, cf *x, hipStream_t st)
 {
-    k_coarsest<float><<<cdiv(n, 4), 256, 0, st>>>(n, Minv, r, x);
+    k_coarsest<float><<<cdiv(n, 4), 256, 0, st>>>(n, Minv, r, x, Batch{});
     HD_LAUNCH_CHECK();
 }
 
@@ -635,8 +668,15 @@ constexpr int ZT_W = 2 * ZT_CX + 3, ZT_H = 2 * ZT_CY + 3;
 template <bool RESID>
 __global__ __launch_bounds__(256) void k_zt(Lev Lf, Lev Lc, int zho, const cd *__restrict__ vf,
                                             const cd *__restrict__ b, cd *__restrict__ vc,
-                                            int tiles_x)
+                                            int tiles_x, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    {
+        const size_t nf = (size_t)Lf.nx * Lf.ny, nc = (size_t)Lc.nx * Lc.ny;
+        vf += blockIdx.y * nf;
+        if (RESID) b += blockIdx.y * nc;
+        vc += blockIdx.y * nc;
+    }
     __shared__ cd sv[ZT_H][ZT_W];
     __shared__ cd sx[ZT_H][ZT_CX];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -682,13 +722,14 @@ __global__ __launch_bounds__(256) void k_zt(Lev Lf, Lev Lc, int zho, const cd *_
 }
 
 hipError_t launch_zt(const Lev &Lf, const Lev &Lc, int zho, const cd *vf, const cd *b, cd *vc,
-                     hipStream_t st)
+                     hipStream_t st, Batch bt)
 {
     const int tx = cdiv(Lc.nx, ZT_CX), ty = cdiv(Lc.ny, ZT_CY);
+    const dim3 g(tx * ty, bt.B);
     if (b)
-        k_zt<true><<<tx * ty, 256, 0, st>>>(Lf, Lc, zho, vf, b, vc, tx);
+        k_zt<true><<<g, 256, 0, st>>>(Lf, Lc, zho, vf, b, vc, tx, bt);
     else
-        k_zt<false><<<tx * ty, 256, 0, st>>>(Lf, Lc, zho, vf, b, vc, tx);
+        k_zt<false><<<g, 256, 0, st>>>(Lf, Lc, zho, vf, b, vc, tx, bt);
     HD_LAUNCH_CHECK();
 }
 
@@ -696,8 +737,11 @@ hipError_t launch_zt(const Lev &Lf, const Lev &Lc, int zho, const cd *vf, const 
 // Deflation prolongation vf = Z vc (thread per fine node, 64 x 4 blocks).
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_z(Lev Lf, Lev Lc, int zho, const cd *__restrict__ vc,
-                                           cd *__restrict__ vf, int tiles_x)
+                                           cd *__restrict__ vf, int tiles_x, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    vc += (size_t)blockIdx.y * Lc.nx * Lc.ny;
+    vf += (size_t)blockIdx.y * Lf.nx * Lf.ny;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i = (t % tiles_x) * 64 + (threadIdx.x & 63);
     const int j = (t / tiles_x) * 4 + (threadIdx.x >> 6);
@@ -707,10 +751,11 @@ __global__ __launch_bounds__(256) void k_z(Lev Lf, Lev Lc, int zho, const cd *__
     vf[(size_t)j * Lf.nx + i] = v;
 }
 
-hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf, hipStream_t st)
+hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf, hipStream_t st,
+                    Batch bt)
 {
     const int tx = cdiv(Lf.nx, 64), ty = cdiv(Lf.ny, 4);
-    k_z<<<tx * ty, 256, 0, st>>>(Lf, Lc, zho, vc, vf, tx);
+    k_z<<<dim3(tx * ty, bt.B), 256, 0, st>>>(Lf, Lc, zho, vc, vf, tx, bt);
     HD_LAUNCH_CHECK();
 }
 
@@ -721,8 +766,15 @@ hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf,
 __global__ __launch_bounds__(256) void k_dresid(Lev Lf, Lev Lc, int zho,
                                                 const cd *__restrict__ v,
                                                 const cd *__restrict__ v2, cd *__restrict__ tout,
-                                                int tiles_x)
+                                                int tiles_x, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    {
+        const size_t nf = (size_t)Lf.nx * Lf.ny, nc = (size_t)Lc.nx * Lc.ny;
+        v += blockIdx.y * nf;
+        tout += blockIdx.y * nf;
+        v2 += blockIdx.y * nc;
+    }
     __shared__ cd sz[VU_H][VU_W];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i0 = (t % tiles_x) * VU_TX, j0 = (t / tiles_x) * VU_TY;
@@ -764,10 +816,10 @@ __global__ __launch_bounds__(256) void k_dresid(Lev Lf, Lev Lc, int zho,
 }
 
 hipError_t launch_dresid(const Lev &Lf, const Lev &Lc, int zho, const cd *v, const cd *v2,
-                         cd *t, hipStream_t st)
+                         cd *t, hipStream_t st, Batch bt)
 {
     const int tx = cdiv(Lf.nx, VU_TX), ty = cdiv(Lf.ny, VU_TY);
-    k_dresid<<<tx * ty, 256, 0, st>>>(Lf, Lc, zho, v, v2, t, tx);
+    k_dresid<<<dim3(tx * ty, bt.B), 256, 0, st>>>(Lf, Lc, zho, v, v2, t, tx, bt);
     HD_LAUNCH_CHECK();
 }
 
@@ -967,8 +1019,15 @@ template <bool RESID, bool VARK, bool GLK1>
 __global__ __launch_bounds__(256) void k_redglk2(Lev L, const cd *__restrict__ u,
                                                  const cd *__restrict__ b, cd *__restrict__ y,
                                                  int tiles_x, int nb_int, int nR, int nC,
-                                                 int count)
+                                                 int count, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    {
+        const size_t off = (size_t)blockIdx.y * L.nx * L.ny;
+        u += off;
+        if (RESID) b += off;
+        y += off;
+    }
     if ((int)blockIdx.x < nb_int)
         redglk2_interior<RESID, VARK>(L, u, b, y, tiles_x, nb_int);
     else
@@ -976,7 +1035,7 @@ __global__ __launch_bounds__(256) void k_redglk2(Lev L, const cd *__restrict__ u
 }
 
 template <bool GLK1>
-static hipError_t redglk_t(const Lev &L, const cd *x, const cd *b, cd *y, hipStream_t st)
+static hipError_t redglk_t(const Lev &L, const cd *x, const cd *b, cd *y, hipStream_t st, Batch bt)
 {
     int tx = 0, nb_int = 0;
     if (L.nx >= 5 && L.ny >= 5) {
@@ -987,27 +1046,29 @@ static hipError_t redglk_t(const Lev &L, const cd *x, const cd *b, cd *y, hipStr
     const int nR = L.ny < 4 ? L.ny : 4, nC = L.nx < 4 ? L.nx : 4;
     const int inner_rows = L.ny - nR;  // rows 2..ny-3 when ny >= 5, else 0
     const int count = nR * L.nx + nC * inner_rows;
-    const int nb = nb_int + cdiv(count, 256);
+    const dim3 g(nb_int + cdiv(count, 256), bt.B);
     if (L.k) {
         if (b)
-            k_redglk2<true, true, GLK1><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count);
+            k_redglk2<true, true, GLK1><<<g, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count,
+                                                          bt);
         else
-            k_redglk2<false, true, GLK1><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC,
-                                                            count);
+            k_redglk2<false, true, GLK1><<<g, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count,
+                                                           bt);
     } else {
         if (b)
-            k_redglk2<true, false, GLK1><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC,
-                                                            count);
+            k_redglk2<true, false, GLK1><<<g, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count,
+                                                           bt);
         else
-            k_redglk2<false, false, GLK1><<<nb, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC,
-                                                             count);
+            k_redglk2<false, false, GLK1><<<g, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC,
+                                                            count, bt);
     }
     HD_LAUNCH_CHECK();
 }
 
-hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, int glk1, hipStream_t st)
+hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, int glk1, hipStream_t st,
+                          Batch bt)
 {
-    return glk1 ? redglk_t<true>(L, x, b, y, st) : redglk_t<false>(L, x, b, y, st);
+    return glk1 ? redglk_t<true>(L, x, b, y, st, bt) : redglk_t<false>(L, x, b, y, st, bt);
 }
 
 // ------------------------------------------------------------------------
@@ -1020,8 +1081,15 @@ hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, int glk
 template <bool RESID>
 __global__ __launch_bounds__(256) void k_redo4(Lev L, const cd *__restrict__ u,
                                                const cd *__restrict__ b, cd *__restrict__ y,
-                                               int tiles_x)
+                                               int tiles_x, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    {
+        const size_t off = (size_t)blockIdx.y * L.nx * L.ny;
+        u += off;
+        if (RESID) b += off;
+        y += off;
+    }
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int I = (t % tiles_x) * 64 + (threadIdx.x & 63);
     const int J = (t / tiles_x) * 4 + (threadIdx.x >> 6);
@@ -1056,13 +1124,14 @@ __global__ __launch_bounds__(256) void k_redo4(Lev L, const cd *__restrict__ u,
     y[p] = o;
 }
 
-hipError_t launch_redo4(const Lev &L, const cd *x, const cd *b, cd *y, hipStream_t st)
+hipError_t launch_redo4(const Lev &L, const cd *x, const cd *b, cd *y, hipStream_t st, Batch bt)
 {
     const int tx = cdiv(L.nx, 64), ty = cdiv(L.ny, 4);
+    const dim3 g(tx * ty, bt.B);
     if (b)
-        k_redo4<true><<<tx * ty, 256, 0, st>>>(L, x, b, y, tx);
+        k_redo4<true><<<g, 256, 0, st>>>(L, x, b, y, tx, bt);
     else
-        k_redo4<false><<<tx * ty, 256, 0, st>>>(L, x, b, y, tx);
+        k_redo4<false><<<g, 256, 0, st>>>(L, x, b, y, tx, bt);
     HD_LAUNCH_CHECK();
 }
 
@@ -1079,11 +1148,11 @@ static int g_resident = 0;  // Krylov blocks resident on the device at once
 
 __global__ void k_mdot(const cd *__restrict__ V, size_t ld, int m, const cd *__restrict__ w,
                        size_t n, size_t chunk, cd *__restrict__ part, int with_norm,
-                       const cd *__restrict__ cond, int jcond);
+                       const cd *__restrict__ cond, int jcond, size_t vbs, size_t wbs, Batch bt);
 __global__ void k_mupdate(cd *__restrict__ w, const cd *__restrict__ V, size_t ld, int m,
                           const cd *__restrict__ c, size_t n, size_t chunk,
                           cd *__restrict__ partn, const cd *__restrict__ cond, int jcond,
-                          const cd *__restrict__ sig);
+                          const cd *__restrict__ sig, size_t vbs, size_t wbs, Batch bt);
 
 static int resident_blocks()
 {
@@ -1157,8 +1226,17 @@ __device__ __forceinline__ bool need_reorth(const cd *__restrict__ hb, int j1)
 __global__ __launch_bounds__(256) void k_mdot(const cd *__restrict__ V, size_t ld, int m,
                                               const cd *__restrict__ w, size_t n, size_t chunk,
                                               cd *__restrict__ part, int with_norm,
-                                              const cd *__restrict__ cond, int jcond)
+                                              const cd *__restrict__ cond, int jcond, size_t vbs,
+                                              size_t wbs, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    {
+        const size_t rb = blockIdx.y;
+        if (V) V += rb * vbs;
+        w += rb * wbs;
+        part += rb * gridDim.x * PSTRIDE;
+        if (cond) cond += rb * SB;
+    }
     if (cond && !need_reorth(cond, jcond)) return;
     __shared__ cd red[4][PSTRIDE];
     const size_t base = (size_t)blockIdx.x * chunk;
@@ -1225,10 +1303,12 @@ __global__ __launch_bounds__(256) void k_mdot(const cd *__restrict__ V, size_t l
 }
 
 hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd *part,
-                       int with_norm, const cd *cond, int jcond, hipStream_t st)
+                       int with_norm, const cd *cond, int jcond, hipStream_t st, Batch bt,
+                       size_t vbs, size_t wbs)
 {
     const int nb = krylov_blocks(n);
-    k_mdot<<<nb, 256, 0, st>>>(V, ld, m, w, n, krylov_chunk(n, nb), part, with_norm, cond, jcond);
+    k_mdot<<<dim3(nb, bt.B), 256, 0, st>>>(V, ld, m, w, n, krylov_chunk(n, nb), part, with_norm,
+                                           cond, jcond, vbs, wbs, bt);
     HD_LAUNCH_CHECK();
 }
 
@@ -1239,8 +1319,19 @@ __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *_
                                                  size_t ld, int m, const cd *__restrict__ c,
                                                  size_t n, size_t chunk, cd *__restrict__ partn,
                                                  const cd *__restrict__ cond, int jcond,
-                                                 const cd *__restrict__ sig)
+                                                 const cd *__restrict__ sig, size_t vbs,
+                                                 size_t wbs, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    {
+        const size_t rb = blockIdx.y;
+        w += rb * wbs;
+        V += rb * vbs;
+        c += rb * SB;
+        if (partn) partn += rb * gridDim.x * PSTRIDE;
+        if (cond) cond += rb * SB;
+        if (sig) sig += rb * SB;
+    }
     if (cond && !need_reorth(cond, jcond)) return;
     __shared__ cd red[4];
     const size_t base = (size_t)blockIdx.x * chunk;
@@ -1303,11 +1394,12 @@ __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *_
 }
 
 hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *partn,
-                          const cd *cond, int jcond, const cd *sig, hipStream_t st)
+                          const cd *cond, int jcond, const cd *sig, hipStream_t st, Batch bt,
+                          size_t vbs, size_t wbs)
 {
     const int nb = krylov_blocks(n);
-    k_mupdate<<<nb, 256, 0, st>>>(w, V, ld, m, c, n, krylov_chunk(n, nb), partn, cond, jcond,
-                                  sig);
+    k_mupdate<<<dim3(nb, bt.B), 256, 0, st>>>(w, V, ld, m, c, n, krylov_chunk(n, nb), partn,
+                                              cond, jcond, sig, vbs, wbs, bt);
     HD_LAUNCH_CHECK();
 }
 
@@ -1320,8 +1412,17 @@ __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int
                                                 cd *__restrict__ out, int mode,
                                                 const cd *__restrict__ cond, int jcond,
                                                 const cd *__restrict__ sig, int nsig,
-                                                cd *__restrict__ sig_out)
+                                                cd *__restrict__ sig_out, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    {
+        const size_t rb = blockIdx.y;
+        part += rb * nblk * PSTRIDE;
+        out += rb * SB;
+        if (cond) cond += rb * SB;
+        if (sig) sig += rb * SB;
+        if (sig_out) sig_out += rb * SB;
+    }
     __shared__ cd red[256];
     const int i = blockIdx.x;
     if (cond && !need_reorth(cond, jcond)) {
@@ -1352,31 +1453,44 @@ __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int
 }
 
 hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, const cd *cond,
-                         int jcond, const cd *sig, int nsig, cd *sig_out, hipStream_t st)
+                         int jcond, const cd *sig, int nsig, cd *sig_out, hipStream_t st,
+                         Batch bt)
 {
-    k_reduce<<<m, 256, 0, st>>>(part, nblk, out, mode, cond, jcond, sig, nsig, sig_out);
+    k_reduce<<<dim3(m, bt.B), 256, 0, st>>>(part, nblk, out, mode, cond, jcond, sig, nsig, sig_out,
+                                            bt);
     HD_LAUNCH_CHECK();
 }
 
 __global__ __launch_bounds__(256) void k_scale(const cd *__restrict__ w, const cd *__restrict__ nrm,
-                                               cd *__restrict__ v, size_t n)
+                                               cd *__restrict__ v, size_t n, size_t wbs,
+                                               size_t vbs, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    w += blockIdx.y * wbs;
+    v += blockIdx.y * vbs;
+    nrm += (size_t)blockIdx.y * SB;
     const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     const double h = nrm[0].x;
     v[p] = h > 0.0 ? cscal(1.0 / h, w[p]) : czero();
 }
 
-hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t st)
+hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t st, Batch bt,
+                        size_t wbs, size_t vbs)
 {
-    k_scale<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(w, nrm, v, n);
+    k_scale<<<dim3((unsigned)((n + 255) / 256), bt.B), 256, 0, st>>>(w, nrm, v, n, wbs, vbs, bt);
     HD_LAUNCH_CHECK();
 }
 
 __global__ __launch_bounds__(256) void k_lincomb(const cd *__restrict__ V, size_t ld, int m,
                                                  const cd *__restrict__ y, cd *__restrict__ out,
-                                                 size_t n, int accumulate)
+                                                 size_t n, int accumulate, size_t vbs,
+                                                 size_t obs, Batch bt)
 {
+    if (skip_rhs(bt)) return;
+    V += blockIdx.y * vbs;
+    out += blockIdx.y * obs;
+    y += (size_t)blockIdx.y * SB;
     const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     cd s = accumulate ? out[p] : czero();
@@ -1385,9 +1499,10 @@ __global__ __launch_bounds__(256) void k_lincomb(const cd *__restrict__ V, size_
 }
 
 hipError_t launch_lincomb(const cd *V, size_t ld, int m, const cd *y, cd *out, size_t n,
-                          int accumulate, hipStream_t st)
+                          int accumulate, hipStream_t st, Batch bt, size_t vbs, size_t obs)
 {
-    k_lincomb<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(V, ld, m, y, out, n, accumulate);
+    k_lincomb<<<dim3((unsigned)((n + 255) / 256), bt.B), 256, 0, st>>>(V, ld, m, y, out, n,
+                                                                       accumulate, vbs, obs, bt);
     HD_LAUNCH_CHECK();
 }
 
@@ -1407,16 +1522,18 @@ hipError_t launch_zero(cd *p, size_t n, hipStream_t st)
 // in and out may be the same buffer (each thread touches one entry)
 __global__ __launch_bounds__(256) void k_mask_copy(Lev L, const cd *in, cd *out)
 {
+    in += (size_t)blockIdx.y * L.nx * L.ny;
+    out += (size_t)blockIdx.y * L.nx * L.ny;
     const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (q >= (size_t)L.nx * L.ny) return;
     const int i = (int)(q % L.nx), j = (int)(q / L.nx);
     out[q] = unknown(L, i, j) ? in[q] : czero();
 }
 
-hipError_t launch_mask_copy(const Lev &L, const cd *in, cd *out, hipStream_t st)
+hipError_t launch_mask_copy(const Lev &L, const cd *in, cd *out, hipStream_t st, int B)
 {
     const size_t n = (size_t)L.nx * L.ny;
-    k_mask_copy<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(L, in, out);
+    k_mask_copy<<<dim3((unsigned)((n + 255) / 256), B), 256, 0, st>>>(L, in, out);
     HD_LAUNCH_CHECK();
 }
 

@@ -1,0 +1,107 @@
+"""Batched multi-right-hand-side path (several right-hand sides of one
+operator in one pass).  Every kernel of the batched path runs the same
+arithmetic per right-hand side as the single path, so each right-hand side of
+a batched call must equal the single-right-hand-side call bit for bit, and
+match the oracle to the usual bars.  Solves mix right-hand sides that converge
+at different iterations (and a zero one) to exercise the active masks."""
+import numpy as np
+import pytest
+
+from paper_2308_06152_amd import inputs
+
+from test_gpu_parity import CASES, H, dev, host, make_pair, rel  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_batched_vcycle_and_apply(H, ora, case):
+    S, P = make_pair(H, ora, case)
+    B = 4
+    r = np.stack([inputs.random_complex((P.ny, P.nx), 150 + q) for q in range(B)])
+    zb = host(S.vcycle(dev(r)))
+    yb = host(S.apply(dev(r)))
+    for q in range(B):
+        zs = host(S.vcycle(dev(r[q])))
+        assert np.array_equal(zb[q], zs)
+        assert rel(zb[q], ora.vcycle(P, r[q])) <= 1e-12
+        assert rel(yb[q], ora.helm_apply(P, r[q])) <= 1e-12
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("case", CASES[:7], ids=[c[0] for c in CASES[:7]])
+def test_batched_deflate_fixed(H, ora, case, mode):
+    n_it = 8
+    S, P = make_pair(H, ora, case, coarse_mode=1, coarse_iters=n_it, coarse_restart=5)
+    Po = P.replace(coarse_mode=ora.CMODE_FIXED, coarse_iters=n_it, coarse_restart=5)
+    B = 3
+    v = np.stack([inputs.random_complex((P.ny, P.nx), 160 + q) for q in range(B)])
+    wb = host(S.deflate(dev(v), mode))
+    for q in range(B):
+        assert np.array_equal(wb[q], host(S.deflate(dev(v[q]), mode)))
+        want, _ = ora.deflate_apply(Po, v[q], mode)
+        assert rel(wb[q], want) <= 1e-11
+
+
+def test_batched_deflate_tol_mode_mixed_convergence(H, ora):
+    """Coarse GMRES to 0.1: right-hand sides of very different smoothness stop
+    at different inner iterations; each still matches its own single call."""
+    case = ("som129", 129, 129, 1, "const", 25.0, 1)
+    S, P = make_pair(H, ora, case, coarse_mode=2, coarse_tol=1e-1, coarse_iters=300,
+                     coarse_restart=7)
+    Po = P.replace(coarse_mode=ora.CMODE_TOL, coarse_tol=1e-1, coarse_iters=300,
+                   coarse_restart=7)
+    x = np.linspace(0, 1, P.nx)
+    smooth = np.outer(np.sin(np.pi * x), np.sin(2 * np.pi * x)) + 0j
+    v = np.stack([inputs.random_complex((P.ny, P.nx), 170), smooth,
+                  np.zeros((P.ny, P.nx), complex), inputs.random_complex((P.ny, P.nx), 171)])
+    wb = host(S.deflate(dev(v), 2))
+    for q in range(len(v)):
+        assert np.array_equal(wb[q], host(S.deflate(dev(v[q]), 2)))
+        if q != 2:
+            want, _ = ora.deflate_apply(Po, v[q], 2)
+            assert rel(wb[q], want) <= 1e-9
+    assert np.abs(wb[2]).max() == 0
+
+
+@pytest.mark.parametrize("bc,cop", [(1, 1), (0, 0)])
+def test_batched_solve_equals_single_solves(H, ora, bc, cop):
+    n, k = 129, 30.0
+    nx, ny, hx, hy = inputs.unit_square(n)
+    S, P = make_pair(H, ora, ("b", n, n, bc, "const", k, cop), coarse_mode=2, coarse_tol=0.1,
+                     coarse_iters=300, coarse_restart=15, restart=20)
+    srcs = [inputs.point_source(nx, ny, hx, hy, 64, 64),
+            inputs.point_source(nx, ny, hx, hy, 20, 100),
+            np.zeros((ny, nx), complex),
+            inputs.gaussian_source(nx, ny, hx, hy, 90, 30, 3 * hx),
+            inputs.point_source(nx, ny, hx, hy, 5, 5) * (1 + 2j)]
+    b = np.stack(srcs)
+    xb, ib = S.solve(dev(b))
+    xb = host(xb)
+    outs = set()
+    for q in range(len(srcs)):
+        xs, iq = S.solve(dev(srcs[q]))
+        assert ib[q]["outer_iters"] == iq[0]["outer_iters"]
+        assert ib[q]["inner_iters_total"] == iq[0]["inner_iters_total"]
+        assert ib[q]["converged"] and iq[0]["converged"]
+        assert np.array_equal(xb[q], host(xs)), q
+        outs.add(ib[q]["outer_iters"])
+        if q != 2:
+            r = ora.helm_apply(P, xb[q]) - srcs[q] * (ora.helm_apply(P, np.ones_like(xb[q])) != 0)
+            assert np.linalg.norm(r) / np.linalg.norm(srcs[q]) <= 1e-6
+    assert len(outs) >= 2  # different right-hand sides stopped at different iterations
+
+
+def test_batched_solve_can_be_switched_off(H, ora):
+    w = inputs.scaled_plain(65, 15.0)
+    S, _ = make_pair(H, ora, ("o", 65, 65, 1, "const", 15.0, 1), coarse_mode=2,
+                     coarse_tol=0.1, coarse_iters=300)
+    S0, _ = make_pair(H, ora, ("o", 65, 65, 1, "const", 15.0, 1), coarse_mode=2,
+                      coarse_tol=0.1, coarse_iters=300, batch=0)
+    assert S0.opts.batch == 0
+    b = np.stack([w.rhs(), 2 * w.rhs()])
+    x1, i1 = S.solve(dev(b))
+    x0, i0 = S0.solve(dev(b))
+    assert torch.equal(x1, x0)
+    assert [i["outer_iters"] for i in i1] == [i["outer_iters"] for i in i0]
