@@ -36,9 +36,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["large", "small", "wedge"], default="large",
+    ap.add_argument("--workload", choices=["large", "small", "wedge", "layered"], default="large",
                     help="large: 4097^2 k=800 Sommerfeld (the headline); small: 129^2 "
-                         "Dirichlet k=20; wedge: the 1153 x 1921 three-layer model at 40 Hz")
+                         "Dirichlet k=20; wedge: the 1153 x 1921 three-layer model at 40 Hz; "
+                         "layered: 2049 x 1025 layered model, --nrhs sources at --freq")
+    ap.add_argument("--nrhs", type=int, default=64, help="layered: sources solved together")
+    ap.add_argument("--freq", type=float, default=10.0, help="layered: frequency in Hz")
+    ap.add_argument("--batch", type=int, choices=[0, 1], default=1,
+                    help="layered: 1 = one batched solve of all sources, 0 = one after another")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="mixed: complex64 fine-grid V-cycle inside the FP64 solve")
     ap.add_argument("--roofline-kernel", default="mdot",
@@ -145,16 +150,20 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    w = {"large": inputs.large_plain, "small": inputs.small_plain,
-         "wedge": inputs.wedge}[a.workload]()
+    if a.workload == "layered":
+        w = inputs.layered(freq=a.freq, nsrc=a.nrhs)
+    else:
+        w = {"large": inputs.large_plain, "small": inputs.small_plain,
+             "wedge": inputs.wedge}[a.workload]()
     kf = w.kfield()
     prec = H.PREC_MIXED if a.precision == "mixed" else H.PREC_FP64
     S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc,
                  k=None if kf is None else torch.from_numpy(kf).cuda(), kconst=w.kconst,
                  coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
                  coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart, restart=w.restart,
-                 tol=w.tol, precision=prec)
-    b = torch.from_numpy(w.rhs()).cuda()
+                 tol=w.tol, precision=prec, batch=a.batch)
+    nrhs = w.nsrc if w.model == "layered" else 1
+    b = torch.from_numpy(w.sources() if nrhs > 1 else w.rhs()).cuda()
     x = torch.zeros_like(b)
     torch.cuda.synchronize()
     for _ in range(a.warmup):
@@ -166,21 +175,21 @@ def main():
     infos = []
     for _ in range(a.steps):
         _, info = S.solve(b, x)
-        infos.append(info[0])
+        infos.append(info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n_launch, k_ms, k_bytes = S.timing_read()
     S.timing_enable(-1, -1)
     elapsed = t1 - t0
-    last = infos[-1]
-    if not all(i["converged"] for i in infos):
+    last = infos[-1][0]
+    if not all(i["converged"] for step in infos for i in step):
         print("bench.py: a solve did not converge", file=sys.stderr)
         sys.exit(1)
     achieved = (k_bytes / 1e9) / (k_ms / 1e3) if k_ms > 0 else 0.0
     traffic = measured_traffic(a.roofline_kernel, w.name) if prec == H.PREC_FP64 else None
     line = {
         "metric": METRIC,
-        "value": a.steps / elapsed,
+        "value": nrhs * a.steps / elapsed,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -194,7 +203,7 @@ def main():
         "config": {
             "workload": w.name + ("_mixed" if prec == H.PREC_MIXED else ""),
             "grid": f"{w.nx}x{w.ny}",
-            "k": w.kconst if kf is None else f"wedge model at {w.freq:g} Hz",
+            "k": w.kconst if kf is None else f"{w.model} model at {w.freq:g} Hz",
             "bc": "sommerfeld" if w.bc == H.BC_SOMMERFELD else "dirichlet",
             "source": "gaussian sigma=2h" if w.source == "gauss" else "point",
             "preconditioner": "APD (Bezier Z, " + ("ReD-Glk2" if w.coarse_op else "Galerkin")
@@ -204,6 +213,10 @@ def main():
             "coarse_solve": f"GMRES({w.coarse_restart}) to {w.coarse_tol:g}",
             "outer_iters": last["outer_iters"], "inner_iters_total": last["inner_iters_total"],
             "relres": last["relres"],
+            **({"nrhs": nrhs, "batched": bool(a.batch),
+                "outer_iters_max": max(i["outer_iters"] for i in infos[-1]),
+                "inner_iters_sum": sum(i["inner_iters_total"] for i in infos[-1]),
+                "relres_max": max(i["relres"] for i in infos[-1])} if nrhs > 1 else {}),
         },
         "roofline": {
             "kernel": a.roofline_kernel, "level": a.roofline_level, "bound": "hbm",

@@ -1079,7 +1079,7 @@ int coarse_apply_b(helm_ctx *h, const cd *x, const cd *b, cd *y, const int *dm)
 // Lazily normalised Arnoldi step of the batched inner GMRES (as
 // arnoldi_lazy_enqueue, for every active right-hand side): basis slot j1
 // already holds A z; projections and the norm go to read-back slot `slot`.
-int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm)
+int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm, int nact)
 {
     BatchWS *W = h->bw;
     const Batch bt{W->B, dm};
@@ -1087,9 +1087,16 @@ int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm)
     const int nb = krylov_blocks(n);
     cd *w = W->Vc + (size_t)j1 * ld;
     cd *h1 = W->hbuf, *h2 = W->hbuf + PSTRIDE, *nr = W->hbuf + 2 * PSTRIDE;
-    HCHK(launch_mdot(W->Vc, ld, j1, w, n, W->part, 1, nullptr, 0, h->st, bt, n, n));
+    {
+        Timed tm(h, HELM_K_DOT, 1, 16.0 * (j1 + 1) * n * nact);
+        HCHK(launch_mdot(W->Vc, ld, j1, w, n, W->part, 1, nullptr, 0, h->st, bt, n, n));
+    }
     HCHK(launch_reduce(W->part, nb, j1 + 1, h1, 0, nullptr, 0, W->sig, j1, nullptr, h->st, bt));
-    HCHK(launch_mupdate(w, W->Vc, ld, j1, h1, n, W->partn, nullptr, 0, W->sig, h->st, bt, n, n));
+    {
+        Timed tm(h, HELM_K_UPDATE, 1, 16.0 * (j1 + 2) * n * nact);
+        HCHK(launch_mupdate(w, W->Vc, ld, j1, h1, n, W->partn, nullptr, 0, W->sig, h->st, bt, n,
+                            n));
+    }
     HCHK(launch_mdot(W->Vc, ld, j1, w, n, W->part, 0, h1, j1, h->st, bt, n, n));
     HCHK(launch_reduce(W->part, nb, j1, h2, 0, h1, j1, W->sig, j1, nullptr, h->st, bt));
     HCHK(launch_mupdate(w, W->Vc, ld, j1, h2, n, W->partn, h1, j1, W->sig, h->st, bt, n, n));
@@ -1110,13 +1117,13 @@ double read_col(const BatchWS *W, int slot, int b, int j1, zc *col)
     return hp[2 * PSTRIDE].x;
 }
 
-int inner_step_b(helm_ctx *h, int j, int slot, const int *dm)
+int inner_step_b(helm_ctx *h, int j, int slot, const int *dm, int nact)
 {
     BatchWS *W = h->bw;
     const size_t ld = (size_t)W->B * h->L[1].n();
     RCHK(vcycle_b(h, 1, W->Vc + (size_t)j * ld, W->zc, 0, nullptr, W->sig + j, dm));
     RCHK(coarse_apply_b(h, W->zc, nullptr, W->Vc + (size_t)(j + 1) * ld, dm));
-    return arnoldi_lazy_b(h, j + 1, slot, dm);
+    return arnoldi_lazy_b(h, j + 1, slot, dm, nact);
 }
 
 // Upload per-right-hand-side least-squares solutions (y[b], zero-padded to
@@ -1202,9 +1209,10 @@ int coarse_solve_b(helm_ctx *h, const cd *bvec, cd *x, const std::vector<char> &
             unorm[b][0] = beta[b];
         }
         const int steps = std::min(m, cap - itmin);
-        RCHK(inner_step_b(h, 0, 0, dm));
+        int nact = nlive;
+        RCHK(inner_step_b(h, 0, 0, dm, nact));
         for (int j = 0; j < steps; j++) {
-            if (j + 1 < steps) RCHK(inner_step_b(h, j + 1, (j + 1) & 1, dm));
+            if (j + 1 < steps) RCHK(inner_step_b(h, j + 1, (j + 1) & 1, dm, nact));
             HCHK(hipEventSynchronize(W->ev[j & 1]));
             bool changed = false;
             int nstep = 0;
@@ -1227,6 +1235,7 @@ int coarse_solve_b(helm_ctx *h, const cd *bvec, cd *x, const std::vector<char> &
             if (changed) {
                 dm = upload_mask(h, stepm);
                 MCHK(dm);
+                nact = nstep;
             }
         }
         // x += V-cycle(sum_i y_i v_i) for every right-hand side of the cycle

@@ -39,8 +39,9 @@ class Workload:
     coarse_restart: int = 30
     coarse_tol: float = 1e-1
     coarse_maxit: int = 300
-    model: str = "const"     # "const" (k = kconst) or "wedge" (k from the velocity model)
+    model: str = "const"     # "const" (k = kconst), "wedge" or "layered" (k from a velocity model)
     freq: float = 0.0        # frequency in Hz for a velocity model
+    nsrc: int = 1            # sources of a multi-source workload
 
     @property
     def npts(self) -> int:
@@ -50,7 +51,15 @@ class Workload:
         """The wavenumber field [ny][nx] (None for a constant k)."""
         if self.model == "wedge":
             return 2.0 * math.pi * self.freq / wedge_velocity(self.nx, self.ny, self.hx, self.hy)
+        if self.model == "layered":
+            return 2.0 * math.pi * self.freq / layered_velocity(self.nx, self.ny, self.hx)
         return None
+
+    def sources(self) -> np.ndarray:
+        """All right-hand sides of a multi-source workload, [nsrc][ny][nx]."""
+        if self.model != "layered":
+            return self.rhs()[None]
+        return layered_sources(self.nx, self.ny, self.hx, self.nsrc)
 
     def rhs(self) -> np.ndarray:
         if self.model == "wedge":
@@ -177,3 +186,47 @@ def wedge(nx: int = 1153, ny: int = 1921, freq: float | None = None) -> Workload
         freq = 40.0 * (nx - 1) / 1152.0
     return Workload(f"wedge_{nx}x{ny}_f{freq:g}", nx, ny, hx, hy, BC_SOMMERFELD, 0.0, "point",
                     COARSE_GALERKIN, model="wedge", freq=freq)
+
+
+# A layered multi-source model for batched solves: 2049 x 1025 nodes at
+# h = 5 m (10240 m x 5120 m), 8 horizontal layers of equal thickness with
+# seeded velocities in [1500, 4500] m/s, and 3 seeded Gaussian anomalies of
+# +-15% (centres in the middle 80% of the domain, widths 200..600 m), so
+# c >= 1275 m/s and kh <= 0.49 at 20 Hz.  Sources: 1/h^2 at i = 16 + 32 s,
+# five nodes below the top edge (row ny - 1 - 5), s = 0 .. nsrc-1.
+def layered_velocity(nx: int, ny: int, h: float, seed: int = SEED) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    c_layers = rng.uniform(1500.0, 4500.0, 8)
+    depth = (ny - 1 - np.arange(ny)) / (ny - 1)            # 0 at the top row, 1 at the bottom
+    layer = np.minimum((depth * 8).astype(int), 7)
+    c = np.repeat(c_layers[layer][:, None], nx, axis=1)
+    X, Y = np.meshgrid(np.arange(nx) * h, np.arange(ny) * h)
+    Lx, Ly = (nx - 1) * h, (ny - 1) * h
+    pert = np.zeros_like(c)
+    for _ in range(3):
+        amp = 0.15 * rng.choice([-1.0, 1.0])
+        cx, cy = rng.uniform(0.1, 0.9) * Lx, rng.uniform(0.1, 0.9) * Ly
+        sig = rng.uniform(200.0, 600.0)
+        pert += amp * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * sig * sig))
+    return c * (1.0 + np.clip(pert, -0.15, 0.15))
+
+
+def layered_sources(nx: int, ny: int, h: float, nsrc: int) -> np.ndarray:
+    b = np.zeros((nsrc, ny, nx), np.complex128)
+    for s in range(nsrc):
+        i = 16 + 32 * s
+        if i >= nx:
+            raise ValueError(f"source {s} at column {i} is outside the {nx}-node grid")
+        b[s, ny - 1 - 5, i] = 1.0 / (h * h)
+    return b
+
+
+def layered(nx: int = 2049, ny: int = 1025, h: float = 5.0, freq: float = 10.0,
+            nsrc: int = 64) -> Workload:
+    """The layered model at one frequency with nsrc sources (one operator, nsrc
+    right-hand sides): Sommerfeld boundary, ReD-Glk2 coarse operator, FGMRES(20)
+    (the outer bases of 64 right-hand sides then take about 90 GB), coarse
+    GMRES(15) to 0.1."""
+    return Workload(f"layered_{nx}x{ny}_f{freq:g}_x{nsrc}", nx, ny, h, h, BC_SOMMERFELD, 0.0,
+                    "point", COARSE_REDGLK2, restart=20, coarse_restart=15, model="layered",
+                    freq=freq, nsrc=nsrc)

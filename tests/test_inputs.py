@@ -44,3 +44,19 @@ def test_wedge_scaled_grids_keep_kh():
     for nx, ny in ((73, 121), (145, 241), (577, 961)):
         w = inputs.wedge(nx, ny)
         assert abs(w.kfield().max() * w.hx - 2 * math.pi * 40 / 1500 * 600 / 1152) < 1e-12
+
+
+def test_layered_model_and_sources():
+    w = inputs.layered()
+    assert (w.nx, w.ny, w.hx) == (2049, 1025, 5.0)
+    c = inputs.layered_velocity(w.nx, w.ny, w.hx)
+    assert c.min() >= 1275.0 - 1e-9 and c.max() <= 4500 * 1.15 + 1e-9
+    # kh <= 0.49 at 20 Hz
+    assert 2 * math.pi * 20 / c.min() * w.hx <= 0.49 + 1e-12
+    # far from the anomalies each layer is constant along x
+    assert len(np.unique(np.round(c[-1, :3], 9))) == 1
+    b = w.sources()
+    assert b.shape == (64, 1025, 2049)
+    for s in (0, 17, 63):
+        assert b[s, 1025 - 1 - 5, 16 + 32 * s] == 1 / 25.0
+        assert np.count_nonzero(b[s]) == 1
