@@ -133,6 +133,9 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(_Info)]
         L.ora_gcr.argtypes = [P, D, D, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                               ctypes.c_int, ctypes.POINTER(_Info)]
+        L.ora_helm_apply_adjoint.argtypes = [P, D, D]
+        L.ora_adjoint_solve.argtypes = [P, D, D]
+        L.ora_grad_s.argtypes = [P, ctypes.c_double, D, D, D]
         _lib = L
     return _lib
 
@@ -306,3 +309,38 @@ def gmres_left(p: Problem, b, tol: float = 1e-6, maxit: int = 200):
                                 ctypes.byref(inf)), "gmres_left")
     del keep
     return x, Info(inf.iters, bool(inf.converged), inf.inner_total, inf.inner_max, inf.relres)
+
+
+def helm_apply_adjoint(p: Problem, x):
+    """y = A_h^H x."""
+    s = (p.ny, p.nx)
+    c, keep = p._c()
+    x = _cin(x, s)
+    y = np.empty(s, np.complex128)
+    _check(lib().ora_helm_apply_adjoint(ctypes.byref(c), _ptr(x), _ptr(y)), "helm_apply_adjoint")
+    del keep
+    return y
+
+
+def adjoint_solve(p: Problem, f):
+    """lambda = A_h^{-H} f (direct)."""
+    s = (p.ny, p.nx)
+    c, keep = p._c()
+    f = _cin(f, s)
+    lam = np.empty(s, np.complex128)
+    _check(lib().ora_adjoint_solve(ctypes.byref(c), _ptr(f), _ptr(lam)), "adjoint_solve")
+    del keep
+    return lam
+
+
+def grad_s(p: Problem, omega: float, u, lam):
+    """Per-node -Re(conj(lambda) dA/ds u), s = (k/omega)^2."""
+    s = (p.ny, p.nx)
+    c, keep = p._c()
+    u = _cin(u, s)
+    lam = _cin(lam, s)
+    g = np.empty(s, np.float64)
+    _check(lib().ora_grad_s(ctypes.byref(c), float(omega), _ptr(u), _ptr(lam),
+                            g.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "grad_s")
+    del keep
+    return g

@@ -1164,6 +1164,89 @@ int ora_direct_solve(const ora_problem *p, const double *b, double *x)
     return rc;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Adjoint state for the gradient of a misfit with respect to s = k^2/omega^2 */
+/* (the model problem of Section 2 with k = omega sqrt(s))                    */
+/* ------------------------------------------------------------------------- */
+
+/* y = A_h^H x, the conjugate transpose of the 5-point operator, by scattering
+ * each row q of A_h: (A^H x)_p = sum_q conj(A_qp) x_q. */
+static void op5_adj(const lvl_t *g, const cplx *x, cplx *y)
+{
+    const size_t n = npts(g);
+    for (size_t q = 0; q < n; q++) y[q] = 0;
+    for (int j = 0; j < g->ny; j++)
+        for (int i = 0; i < g->nx; i++) {
+            if (!is_unknown(g, i, j)) continue;
+            size_t q = (size_t)j * g->nx + i;
+            cplx c[5];
+            stencil5(g, 1.0, i, j, c);
+            y[q] += conj(c[0]) * x[q];
+            if (c[1] != 0) y[q - 1] += conj(c[1]) * x[q];
+            if (c[2] != 0) y[q + 1] += conj(c[2]) * x[q];
+            if (c[3] != 0) y[q - g->nx] += conj(c[3]) * x[q];
+            if (c[4] != 0) y[q + g->nx] += conj(c[4]) * x[q];
+        }
+}
+
+static void op5_adj_cb(const void *ctx, const cplx *x, cplx *y)
+{
+    op5_adj((const lvl_t *)ctx, x, y);
+}
+
+int ora_helm_apply_adjoint(const ora_problem *p, const double *x, double *y)
+{
+    hier_t H;
+    int rc = build_hier(p, &H);
+    if (rc) return rc;
+    op5_adj(&H.L[0], (const cplx *)x, (cplx *)y);
+    free_hier(&H);
+    return ORA_OK;
+}
+
+/* lambda = A_h^{-H} f by banded LU of the conjugate transpose. */
+int ora_adjoint_solve(const ora_problem *p, const double *f, double *lambda)
+{
+    hier_t H;
+    int rc = build_hier(p, &H);
+    if (rc) return rc;
+    rc = direct_solve_op(&H.L[0], 1, 1, op5_adj_cb, &H.L[0], (const cplx *)f, (cplx *)lambda);
+    free_hier(&H);
+    return rc;
+}
+
+/* g[p] = -Re(conj(lambda_p) (dA/ds_p) u_p): the gradient of
+ * J = 1/2 ||R u - d||^2 with A u = b and A^H lambda = R^T (R u - d).  Only
+ * the diagonal of row p depends on s_p: d/ds of -k^2 is -omega^2, and of the
+ * Sommerfeld term -2ik/h (per eliminated direction) it is -i omega/(h sqrt s)
+ * since k = omega sqrt(s).  Non-unknown (Dirichlet boundary) nodes get 0. */
+int ora_grad_s(const ora_problem *p, double omega, const double *uin, const double *lin,
+               double *g)
+{
+    hier_t H;
+    int rc = build_hier(p, &H);
+    if (rc) return rc;
+    const lvl_t *L = &H.L[0];
+    const cplx *u = (const cplx *)uin, *lam = (const cplx *)lin;
+    for (int j = 0; j < L->ny; j++)
+        for (int i = 0; i < L->nx; i++) {
+            size_t q = (size_t)j * L->nx + i;
+            g[q] = 0;
+            if (!is_unknown(L, i, j)) continue;
+            cplx d = -omega * omega;
+            if (L->bc == ORA_BC_SOMMERFELD) {
+                double sq = L->k[q] / omega; /* sqrt(s) */
+                double w = 0;
+                if (i == 0 || i == L->nx - 1) w += 1.0 / L->hx;
+                if (j == 0 || j == L->ny - 1) w += 1.0 / L->hy;
+                if (w != 0 && sq > 0) d += -IU * omega * w / sq;
+            }
+            g[q] = -creal(conj(lam[q]) * d * u[q]);
+        }
+    free_hier(&H);
+    return ORA_OK;
+}
+
 /* Zero the non-unknown (Dirichlet boundary) entries of a fine vector. */
 static void mask_unknowns(const lvl_t *g, cplx *v)
 {

@@ -112,6 +112,13 @@ int ora_gcr(const ora_problem *p, const double *b, double *x, int restart, doubl
  * stopping on the preconditioned relative residual. */
 int ora_gmres_left(const ora_problem *p, const double *b, double *x, double tol,
                    int maxit, ora_info *info);
+/* y = A_h^H x (conjugate transpose); lambda = A_h^{-H} f (banded LU). */
+int ora_helm_apply_adjoint(const ora_problem *p, const double *x, double *y);
+int ora_adjoint_solve(const ora_problem *p, const double *f, double *lambda);
+/* g = -Re(conj(lambda) (dA/ds) u) per node, s = (k/omega)^2: the adjoint-state
+ * gradient of 1/2 ||R u - d||^2 for A u = b, A^H lambda = R^T (R u - d). */
+int ora_grad_s(const ora_problem *p, double omega, const double *u, const double *lambda,
+               double *g);
 /* x = A_h^{-1} b by banded LU with partial pivoting. */
 int ora_direct_solve(const ora_problem *p, const double *b, double *x);
 /* Same for A_2h (the coarse operator) and for M on level `level`. */

@@ -700,3 +700,84 @@ def test_gcr_exact_preconditioner_one_iteration(ora):
     b = inputs.random_complex((17, 17), 23)
     _, inf = ora.gcr(p, b, tol=1e-10)
     assert inf.converged and inf.iters == 1
+
+
+# ---------------------------------------------------------------------------
+# Adjoint state and the gradient with respect to s = 1/c^2 (k = omega sqrt(s))
+# ---------------------------------------------------------------------------
+def _adj_problem(ora, nx, ny, bc, s, omega):
+    h = 1.0 / (max(nx, ny) - 1)
+    return ora.Problem(nx, ny, h, h, bc=bc, k=omega * np.sqrt(s))
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_adjoint_operator_is_the_conjugate_transpose(ora, bc):
+    nx, ny, omega = 17, 13, 9.0
+    s = inputs.random_field(ny, nx, 0.5, 2.0, seed=31)
+    p = _adj_problem(ora, nx, ny, bc, s, omega)
+    x = inputs.random_complex((ny, nx), 32)
+    lam = inputs.random_complex((ny, nx), 33)
+    if bc == 0:
+        x, lam = _interior(x), _interior(lam)
+    lhs = np.vdot(ora.helm_apply_adjoint(p, lam), x)
+    rhs = np.vdot(lam, ora.helm_apply(p, x))
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+    # the complex-symmetric scaling (D A symmetric, D = 1/2 per eliminated
+    # direction) gives A^H = D conj(A) D^-1
+    if bc == 1:
+        D = np.ones((ny, nx))
+        D[:, 0] *= 0.5
+        D[:, -1] *= 0.5
+        D[0, :] *= 0.5
+        D[-1, :] *= 0.5
+        alt = D * np.conj(ora.helm_apply(p, np.conj(lam / D)))
+        assert np.abs(alt - ora.helm_apply_adjoint(p, lam)).max() <= 1e-12 * np.abs(alt).max()
+    f = inputs.random_complex((ny, nx), 34)
+    if bc == 0:
+        f = _interior(f)
+    lam = ora.adjoint_solve(p, f)
+    assert np.linalg.norm(ora.helm_apply_adjoint(p, lam) - f) <= 1e-11 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_gradient_matches_finite_differences(ora, bc):
+    """Adjoint-state gradient of J(s) = 1/2 sum_shots ||R u - d||^2 against
+    central differences of J evaluated with direct solves, at interior, edge
+    and corner nodes (the Sommerfeld term depends on s through k)."""
+    nx, ny, omega = 17, 13, 11.0
+    h = 1.0 / 16
+    s = inputs.random_field(ny, nx, 0.6, 1.8, seed=35)
+    shots = [(3, ny - 3), (12, ny - 3)]
+    rec = [(i, ny - 2) for i in range(1, nx - 1, 3)] + [(nx - 2, 2)]
+    rng = np.random.default_rng(36)
+    d = [rng.standard_normal(len(rec)) + 1j * rng.standard_normal(len(rec)) for _ in shots]
+
+    def J_and_fields(sv):
+        p = _adj_problem(ora, nx, ny, bc, sv, omega)
+        J, us, fs = 0.0, [], []
+        for (si, sj), dq in zip(shots, d):
+            b = np.zeros((ny, nx), complex)
+            b[sj, si] = 1 / (h * h)
+            u = ora.direct_solve(p, b)
+            r = np.array([u[j, i] for i, j in rec]) - dq
+            J += 0.5 * np.vdot(r, r).real
+            f = np.zeros((ny, nx), complex)
+            for (i, j), rv in zip(rec, r):
+                f[j, i] += rv
+            us.append(u)
+            fs.append(f)
+        return J, us, fs, p
+
+    J0, us, fs, p = J_and_fields(s)
+    g = sum(ora.grad_s(p, omega, u, ora.adjoint_solve(p, f)) for u, f in zip(us, fs))
+    cells = [(8, 6), (0, 6), (8, 0), (0, 0), (16, 12), (3, 10), (1, 1)]
+    for i, j in cells:
+        if bc == 0 and (i in (0, nx - 1) or j in (0, ny - 1)):
+            assert g[j, i] == 0
+            continue
+        eps = 1e-6 * s[j, i]
+        sp, sm = s.copy(), s.copy()
+        sp[j, i] += eps
+        sm[j, i] -= eps
+        fd = (J_and_fields(sp)[0] - J_and_fields(sm)[0]) / (2 * eps)
+        assert abs(fd - g[j, i]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(g).max()), (i, j, fd, g[j, i])
