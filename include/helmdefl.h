@@ -181,6 +181,35 @@ int deflate_apply(helm_ctx *h, int mode, const void *v, void *w, int nrhs);
  * finite. */
 int helm_solve(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *info);
 
+/* ---- Adjoint state: gradient of a misfit with respect to s = 1/c^2 -------
+ * For k = omega sqrt(s) (Section 2) and J = 1/2 sum ||R u - d||^2 with
+ * A_h u = b, the gradient is g = -Re(conj(lambda) (dA_h/ds) u) summed over the
+ * sources, with A_h^H lambda = R^T (R u - d). */
+
+/* lambda = A_h^{-H} f for nrhs right-hand sides ([nrhs][ny][nx], device).
+ * D A_h is complex symmetric for the diagonal D that halves each
+ * Sommerfeld-eliminated direction, so the adjoint solve is the forward solve
+ * (helm_solve with the handle's options, x0 = 0) of conj(D^{-1} f), mapped back
+ * by lambda = D conj(.).  info as for helm_solve (may be NULL); returns
+ * HELM_ENOCONV like helm_solve.  Synchronises. */
+int helm_adjoint_solve(helm_ctx *h, const void *f, void *lambda, int nrhs, helm_solve_info *info);
+
+/* g[p] += sum over the nrhs right-hand sides of -Re(conj(lambda_p) d_p u_p),
+ * d_p = dA_pp/ds_p = -omega^2 (- i omega^2 / k_p per Sommerfeld-eliminated
+ * direction, divided by hx or hy; omitted where k_p = 0).  u, lambda:
+ * [nrhs][ny][nx] complex128; g: real FP64 [ny][nx], device, accumulated.
+ * omega > 0 is the angular frequency with which the handle's k was formed. */
+int helm_gradient_s(helm_ctx *h, double omega, const void *u, const void *lambda, int nrhs,
+                    double *g);
+
+/* Receiver residuals for nrhs wavefields: res[b][r] = u_b[rec[r]] - d[b][r],
+ * f_b = R^T res_b (zero away from the receivers: the adjoint source) and
+ * J[b] = 1/2 ||res_b||^2.  rec: device int array of nrec distinct node indices
+ * j*nx + i (HELM_EINVAL otherwise); d, res: device complex128 [nrhs][nrec];
+ * f: device [nrhs][ny][nx]; J: device double [nrhs]. */
+int helm_receivers(helm_ctx *h, const int *rec, int nrec, const void *u, const void *d, int nrhs,
+                   void *res, void *f, double *J);
+
 /* Free the handle and its device memory (after synchronising its stream). */
 int helm_destroy(helm_ctx *h);
 

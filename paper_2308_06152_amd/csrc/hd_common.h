@@ -162,6 +162,17 @@ hipError_t launch_redglk2(const Lev &Lc, const cd *x, const cd *b, cd *y, int gl
 hipError_t launch_redo4(const Lev &Lc, const cd *x, const cd *b, cd *y, hipStream_t st,
                         Batch bt = Batch{});
 
+// ---- adjoint state ----
+// mode 0: out = conj(in / D), mode 1: out = D conj(in), D = 1/2 per
+// Sommerfeld-eliminated direction (B contiguous vectors).
+hipError_t launch_adj_map(const Lev &L, const cd *in, cd *out, int mode, int B, hipStream_t st);
+// g += sum_b -Re(conj(lam_b) (dA/ds) u_b), s = (k/omega)^2.
+hipError_t launch_grad_s(const Lev &L, double omega, const cd *u, const cd *lam, int B, double *g,
+                         hipStream_t st);
+// res = R u - d, f = R^T res (f pre-zeroed), J = 1/2 ||res||^2 per right-hand side.
+hipError_t launch_receivers(const int *rec, int nrec, const cd *u, const cd *d, size_t n, int B,
+                            cd *res, cd *f, double *J, hipStream_t st);
+
 // ---- Krylov kernels ----
 // Number of partial-sum blocks used for vectors of length n.
 int krylov_blocks(size_t n);

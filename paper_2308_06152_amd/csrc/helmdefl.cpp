@@ -162,6 +162,8 @@ struct helm_ctx {
     cd *V = nullptr, *Z = nullptr, *w = nullptr, *bm = nullptr;
     cd *w2 = nullptr, *r = nullptr;  // GCR / left GMRES work vectors
     BatchWS *bw = nullptr;           // batched solves (allocated on first use)
+    cd *adjb = nullptr;              // adjoint solve right-hand sides
+    size_t adjb_n = 0;
 
     // kernel timing
     int t_cls = -1, t_lev = -1;
@@ -1547,6 +1549,7 @@ void release(helm_ctx *h)
     }
     for (auto e : h->ev_free) (void)hipEventDestroy(e);
     free_batch(h->bw);
+    dfree(h->adjb);
     delete h;
 }
 
@@ -1795,9 +1798,8 @@ int deflate_apply(helm_ctx *h, int mode, const void *v, void *w, int nrhs)
     return HELM_OK;
 }
 
-int helm_solve(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *info)
+static int solve_dispatch(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *info)
 {
-    if (!valid(h) || !b || !x || nrhs < 1) return HELM_EINVAL;
     const size_t n = h->L[0].n();
     int worst = HELM_OK;
     try {
@@ -1818,6 +1820,65 @@ int helm_solve(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *i
         return HELM_ENOMEM;
     }
     return worst;
+}
+
+int helm_solve(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *info)
+{
+    if (!valid(h) || !b || !x || nrhs < 1) return HELM_EINVAL;
+    return solve_dispatch(h, b, x, nrhs, info);
+}
+
+int helm_adjoint_solve(helm_ctx *h, const void *f, void *lambda, int nrhs, helm_solve_info *info)
+{
+    if (!valid(h) || !f || !lambda || nrhs < 1) return HELM_EINVAL;
+    const size_t n = h->L[0].n(), need = (size_t)nrhs * n;
+    if (h->adjb_n < need) {
+        HCHK(hipStreamSynchronize(h->st));
+        dfree(h->adjb);
+        h->adjb = nullptr;
+        h->adjb_n = 0;
+        RCHK(dalloc(&h->adjb, need));
+        h->adjb_n = need;
+    }
+    const Lev L0 = h->lev(0);
+    HCHK(launch_adj_map(L0, (const cd *)f, h->adjb, 0, nrhs, h->st));
+    const int x0 = h->o.x0_given;
+    h->o.x0_given = 0;
+    const int rc = solve_dispatch(h, h->adjb, lambda, nrhs, info);
+    h->o.x0_given = x0;
+    if (rc != HELM_OK && rc != HELM_ENOCONV) return rc;
+    HCHK(launch_adj_map(L0, (const cd *)lambda, (cd *)lambda, 1, nrhs, h->st));
+    HCHK(hipStreamSynchronize(h->st));
+    return rc;
+}
+
+int helm_gradient_s(helm_ctx *h, double omega, const void *u, const void *lambda, int nrhs,
+                    double *g)
+{
+    if (!valid(h) || !u || !lambda || !g || nrhs < 1) return HELM_EINVAL;
+    if (!(omega > 0) || !std::isfinite(omega)) return HELM_EINVAL;
+    HCHK(launch_grad_s(h->lev(0), omega, (const cd *)u, (const cd *)lambda, nrhs, g, h->st));
+    return HELM_OK;
+}
+
+int helm_receivers(helm_ctx *h, const int *rec, int nrec, const void *u, const void *d, int nrhs,
+                   void *res, void *f, double *J)
+{
+    if (!valid(h) || !rec || !u || !d || !res || !f || !J || nrhs < 1 || nrec < 1)
+        return HELM_EINVAL;
+    const size_t n = h->L[0].n();
+    // receiver nodes: inside the grid and distinct (f = R^T res is a scatter)
+    std::vector<int> hr(nrec);
+    HCHK(hipMemcpyAsync(hr.data(), rec, nrec * sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HCHK(hipStreamSynchronize(h->st));
+    for (int v : hr)
+        if (v < 0 || (size_t)v >= n) return HELM_EINVAL;
+    std::sort(hr.begin(), hr.end());
+    if (std::adjacent_find(hr.begin(), hr.end()) != hr.end()) return HELM_EINVAL;
+    HCHK(launch_zero((cd *)f, (size_t)nrhs * n, h->st));
+    HCHK(launch_receivers(rec, nrec, (const cd *)u, (const cd *)d, n, nrhs, (cd *)res, (cd *)f, J,
+                          h->st));
+    return HELM_OK;
 }
 
 const char *helm_strerror(int code)

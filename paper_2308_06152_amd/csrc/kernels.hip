@@ -1136,6 +1136,123 @@ hipError_t launch_redo4(const Lev &L, const cd *x, const cd *b, cd *y, hipStream
 }
 
 // ------------------------------------------------------------------------
+// Adjoint state.  D A_h is complex symmetric for the D that halves each
+// Sommerfeld-eliminated direction (the ghost closure doubles the inward
+// coupling), so A_h^H = D conj(A_h) D^{-1} and A_h^{-H} f = D conj(A_h^{-1}
+// conj(D^{-1} f)): the adjoint solve is a forward solve between two
+// element-wise maps.  mode 0: out = conj(in / D); mode 1: out = D conj(in).
+// Dirichlet boundary nodes are not unknowns (D = 1 elsewhere): out = 0 there.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double dscale(const Lev &L, int i, int j)
+{
+    if (L.bc != BC_SOM) return 1.0;
+    double d = 1.0;
+    if (i == 0 || i == L.nx - 1) d *= 0.5;
+    if (j == 0 || j == L.ny - 1) d *= 0.5;
+    return d;
+}
+
+__global__ __launch_bounds__(256) void k_adj_map(Lev L, const cd *in, cd *out, int mode)
+{
+    const size_t n = (size_t)L.nx * L.ny;
+    in += blockIdx.y * n;
+    out += blockIdx.y * n;
+    const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int i = (int)(q % L.nx), j = (int)(q / L.nx);
+    cd o = czero();
+    if (unknown(L, i, j)) {
+        const double d = dscale(L, i, j);
+        const cd v = in[q];
+        const double c = mode == 0 ? 1.0 / d : d;
+        o = make_double2(c * v.x, -c * v.y);
+    }
+    out[q] = o;
+}
+
+hipError_t launch_adj_map(const Lev &L, const cd *in, cd *out, int mode, int B, hipStream_t st)
+{
+    const size_t n = (size_t)L.nx * L.ny;
+    k_adj_map<<<dim3((unsigned)((n + 255) / 256), B), 256, 0, st>>>(L, in, out, mode);
+    HD_LAUNCH_CHECK();
+}
+
+// g[p] += sum over the B right-hand sides of -Re(conj(lambda_p) (dA/ds)_pp u_p)
+// with s = (k/omega)^2: (dA/ds)_pp = -omega^2, plus -i omega^2 / k_p times
+// (1/hx per eliminated x direction + 1/hy per y direction) on Sommerfeld
+// boundary nodes (the derivative of -2ik/h through k = omega sqrt(s); dropped
+// where k_p = 0).  One thread per node, looping over the right-hand sides.
+__global__ __launch_bounds__(256) void k_grad_s(Lev L, double omega, const cd *__restrict__ u,
+                                                const cd *__restrict__ lam, int B,
+                                                double *__restrict__ g)
+{
+    const size_t n = (size_t)L.nx * L.ny;
+    const size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int i = (int)(q % L.nx), j = (int)(q / L.nx);
+    if (!unknown(L, i, j)) return;
+    double dr = -omega * omega, di = 0.0;
+    if (L.bc == BC_SOM) {
+        double w = 0.0;
+        if (i == 0 || i == L.nx - 1) w += 1.0 / L.hx;
+        if (j == 0 || j == L.ny - 1) w += 1.0 / L.hy;
+        const double k = kat(L, i, j);
+        if (w != 0.0 && k > 0.0) di = -omega * omega * w / k;
+    }
+    double acc = 0.0;
+    for (int b = 0; b < B; b++) {
+        const cd uv = u[(size_t)b * n + q], lv = lam[(size_t)b * n + q];
+        // t = d * u; contribution -Re(conj(lambda) t)
+        const double tr = dr * uv.x - di * uv.y, ti = dr * uv.y + di * uv.x;
+        acc -= lv.x * tr + lv.y * ti;
+    }
+    g[q] += acc;
+}
+
+hipError_t launch_grad_s(const Lev &L, double omega, const cd *u, const cd *lam, int B, double *g,
+                         hipStream_t st)
+{
+    const size_t n = (size_t)L.nx * L.ny;
+    k_grad_s<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(L, omega, u, lam, B, g);
+    HD_LAUNCH_CHECK();
+}
+
+// Receivers: res[b][r] = u_b[rec[r]] - d[b][r]; f_b[rec[r]] = res[b][r] (f must
+// hold zeros; receiver nodes are distinct); J[b] = 1/2 sum_r |res[b][r]|^2.
+// One block per right-hand side.
+__global__ __launch_bounds__(256) void k_receivers(const int *__restrict__ rec, int nrec,
+                                                   const cd *__restrict__ u,
+                                                   const cd *__restrict__ d, size_t n,
+                                                   cd *__restrict__ res, cd *__restrict__ f,
+                                                   double *__restrict__ J)
+{
+    __shared__ double red[256];
+    const size_t b = blockIdx.x;
+    double acc = 0.0;
+    for (int r = threadIdx.x; r < nrec; r += 256) {
+        const size_t node = (size_t)rec[r];
+        const cd v = csub(u[b * n + node], d[b * nrec + r]);
+        res[b * nrec + r] = v;
+        f[b * n + node] = v;
+        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) J[b] = 0.5 * red[0];
+}
+
+hipError_t launch_receivers(const int *rec, int nrec, const cd *u, const cd *d, size_t n, int B,
+                            cd *res, cd *f, double *J, hipStream_t st)
+{
+    k_receivers<<<B, 256, 0, st>>>(rec, nrec, u, d, n, res, f, J);
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
 // Krylov kernels.  Vectors of length n; a basis V holds m vectors at stride
 // ld.  The grid is sized to the number of blocks the chip holds at once
 // (times a whole number of rounds), and each block owns one contiguous chunk

@@ -32,7 +32,8 @@ EXPORTED = [
     "helm_opts_default", "helm_create", "helm_apply", "cslp_vcycle", "deflate_apply",
     "helm_solve", "helm_destroy", "helm_strerror", "helm_coarse_dims", "helm_num_levels",
     "helm_level_dims", "helm_z_restrict", "helm_z_prolong", "helm_coarse_apply",
-    "helm_coarse_solve", "helm_timing_enable", "helm_timing_read",
+    "helm_coarse_solve", "helm_timing_enable", "helm_timing_read", "helm_adjoint_solve",
+    "helm_gradient_s", "helm_receivers",
 ]
 
 
@@ -96,6 +97,9 @@ def load() -> ctypes.CDLL:
     L.helm_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong),
                                    ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double)]
+    L.helm_adjoint_solve.argtypes = [vp, vp, vp, cint, ctypes.POINTER(SolveInfo)]
+    L.helm_gradient_s.argtypes = [vp, ctypes.c_double, vp, vp, cint, vp]
+    L.helm_receivers.argtypes = [vp, vp, cint, vp, vp, cint, vp, vp, vp]
     _lib = L
     return L
 
@@ -247,6 +251,51 @@ class Solver:
         check(load().helm_coarse_solve(self.h, _ptr(v1), _ptr(out), ctypes.byref(it)),
               "helm_coarse_solve")
         return out, it.value
+
+    # adjoint state ------------------------------------------------------
+    def adjoint_solve(self, f, out=None, raise_on_noconv: bool = False):
+        """(lambda, [info per right-hand side]): lambda = A_h^{-H} f."""
+        import torch
+        out = torch.empty_like(f) if out is None else out
+        n = self._nrhs(f, (self.ny, self.nx))
+        infos = (SolveInfo * n)()
+        rc = load().helm_adjoint_solve(self.h, _ptr(f), _ptr(out), n, infos)
+        if rc != HELM_OK and (rc != HELM_ENOCONV or raise_on_noconv):
+            raise HelmError(rc, "helm_adjoint_solve")
+        return out, [i.as_dict() for i in infos]
+
+    def gradient_s(self, omega: float, u, lam, g=None):
+        """g (+)= -Re(conj(lambda) dA/ds u) summed over right-hand sides, as a
+        float64 [ny][nx] tensor."""
+        import torch
+        if g is None:
+            g = torch.zeros((self.ny, self.nx), dtype=torch.float64, device=u.device)
+        if not (g.is_cuda and g.dtype == torch.float64 and g.is_contiguous()
+                and tuple(g.shape) == (self.ny, self.nx)):
+            raise TypeError("g must be a contiguous CUDA float64 (ny, nx) tensor")
+        n = self._nrhs(u, (self.ny, self.nx))
+        if self._nrhs(lam, (self.ny, self.nx)) != n:
+            raise ValueError("u and lambda hold different numbers of right-hand sides")
+        check(load().helm_gradient_s(self.h, float(omega), _ptr(u), _ptr(lam), n,
+                                     g.data_ptr()), "helm_gradient_s")
+        return g
+
+    def receivers(self, rec, u, d):
+        """(res, f, J): res = R u - d, f = R^T res, J = 1/2 ||res||^2 per
+        right-hand side.  rec: CUDA int32 node indices j*nx + i; d: [nrhs][nrec]."""
+        import torch
+        if not (rec.is_cuda and rec.dtype == torch.int32 and rec.is_contiguous()):
+            raise TypeError("rec must be a contiguous CUDA int32 tensor")
+        n = self._nrhs(u, (self.ny, self.nx))
+        nrec = int(rec.numel())
+        if int(d.numel()) != n * nrec:
+            raise ValueError(f"d must hold nrhs x nrec = {n} x {nrec} values")
+        res = torch.empty((n, nrec), dtype=torch.complex128, device=u.device)
+        f = torch.empty((n, self.ny, self.nx), dtype=torch.complex128, device=u.device)
+        J = torch.empty(n, dtype=torch.float64, device=u.device)
+        check(load().helm_receivers(self.h, rec.data_ptr(), nrec, _ptr(u), _ptr(d), n,
+                                    _ptr(res), _ptr(f), J.data_ptr()), "helm_receivers")
+        return res, f, J
 
     # timing -------------------------------------------------------------
     def timing_enable(self, kclass: int, level: int = -1):

@@ -230,3 +230,36 @@ def layered(nx: int = 2049, ny: int = 1025, h: float = 5.0, freq: float = 10.0,
     return Workload(f"layered_{nx}x{ny}_f{freq:g}_x{nsrc}", nx, ny, h, h, BC_SOMMERFELD, 0.0,
                     "point", COARSE_REDGLK2, restart=20, coarse_restart=15, model="layered",
                     freq=freq, nsrc=nsrc)
+
+
+# The adjoint-gradient case: the layered model's physical domain (10240 m x
+# 5120 m) on an nx x ny grid (1025 x 513 at h = 10 m), one frequency (10 Hz
+# there; scaled with 1/h on coarser grids to keep kh), nshot sources at
+# i = 32 + 64 s and nrec receivers spread evenly over i = 2 .. 1022 (i = 2 + 4 r
+# for 256 of them) on the row five nodes below the top edge (positions scaled
+# with the grid).  The "true" model adds one
+# seeded +10% Gaussian anomaly (width 400 m) to the layered model; the initial
+# model is the layered model itself.
+def adjoint_case(nx: int = 1025, ny: int = 513, nshot: int = 16, nrec: int = 256,
+                 seed: int = SEED + 1):
+    h = 10240.0 / (nx - 1)
+    if abs(h * (ny - 1) - 5120.0) > 1e-9:
+        raise ValueError("the grid must span 10240 m x 5120 m")
+    freq = 10.0 * 10.0 / h
+    c0 = layered_velocity(nx, ny, h)
+    rng = np.random.default_rng(seed)
+    X, Y = np.meshgrid(np.arange(nx) * h, np.arange(ny) * h)
+    cx, cy = rng.uniform(0.3, 0.7) * 10240.0, rng.uniform(0.3, 0.7) * 5120.0
+    c_true = c0 * (1.0 + 0.10 * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * 400.0 ** 2)))
+    scale = (nx - 1) / 1024.0
+    jrow = ny - 1 - 5
+    src_i = [int(round((32 + 64 * q) * scale)) for q in range(nshot)]
+    rec_i = [int(round((2 + r * 1020.0 / max(nrec - 1, 1)) * scale)) for r in range(nrec)]
+    if len(set(rec_i)) != nrec or max(src_i + rec_i) >= nx:
+        raise ValueError("sources/receivers do not fit this grid")
+    sources = np.zeros((nshot, ny, nx), np.complex128)
+    for q, i in enumerate(src_i):
+        sources[q, jrow, i] = 1.0 / (h * h)
+    rec = np.array([jrow * nx + i for i in rec_i], np.int32)
+    return dict(nx=nx, ny=ny, h=h, freq=freq, s_true=1.0 / c_true ** 2, s_init=1.0 / c0 ** 2,
+                sources=sources, rec=rec)
