@@ -36,10 +36,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["large", "small", "wedge", "layered"], default="large",
+    ap.add_argument("--workload", choices=["large", "small", "wedge", "layered", "adjoint"],
+                    default="large",
                     help="large: 4097^2 k=800 Sommerfeld (the headline); small: 129^2 "
                          "Dirichlet k=20; wedge: the 1153 x 1921 three-layer model at 40 Hz; "
-                         "layered: 2049 x 1025 layered model, --nrhs sources at --freq")
+                         "layered: 2049 x 1025 layered model, --nrhs sources at --freq; "
+                         "adjoint: misfit gradients on 1025 x 513 with 16 shots at 10 Hz")
     ap.add_argument("--nrhs", type=int, default=64, help="layered: sources solved together")
     ap.add_argument("--freq", type=float, default=10.0, help="layered: frequency in Hz")
     ap.add_argument("--batch", type=int, choices=[0, 1], default=1,
@@ -128,6 +130,51 @@ def cpu_baseline(w, info, coarsest_nodes):
     }
 
 
+def adjoint_bench(a, torch, H, inputs):
+    """Misfit gradients per second: one step = one forward (batched over the
+    shots) + adjoint solve + gradient accumulation, J(s) and dJ/ds."""
+    from paper_2308_06152_amd import adjoint
+    c = inputs.adjoint_case()
+    omega = 2 * 3.141592653589793 * c["freq"]
+    grid = (c["nx"], c["ny"], c["h"], c["h"], H.BC_SOMMERFELD)
+    opts = dict(coarse_op=H.COARSE_REDGLK2, coarse_mode=H.CMODE_TOL, coarse_tol=0.1,
+                coarse_iters=300, coarse_restart=15, restart=20, tol=1e-6, batch=a.batch)
+    src = torch.from_numpy(c["sources"]).cuda()
+    rec = torch.from_numpy(c["rec"]).cuda()
+    kt = (omega * torch.sqrt(torch.from_numpy(c["s_true"]))).cuda()
+    St = H.Solver(c["nx"], c["ny"], c["h"], c["h"], H.BC_SOMMERFELD, k=kt, **opts)
+    ut, _ = St.solve(src)
+    d_obs = ut.reshape(len(c["sources"]), -1)[:, rec.long()].contiguous()
+    St.close()
+    s0 = torch.from_numpy(c["s_init"]).cuda()
+
+    def step():
+        s = s0.clone().requires_grad_(True)
+        J = adjoint.misfit(s, omega, grid, src, rec, d_obs, **opts)
+        J.backward()
+        return J.item(), s.grad
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        J, g = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    line = {
+        "metric": "misfit gradients/s (forward + adjoint solves of all shots, gradient)",
+        "value": a.steps / el, "unit": "gradients/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"adjoint_{c['nx']}x{c['ny']}_f{c['freq']:g}_shots{len(src)}",
+                   "grid": f"{c['nx']}x{c['ny']}", "h_m": c["h"], "freq_hz": c["freq"],
+                   "shots": len(src), "receivers": int(rec.numel()), "batched": bool(a.batch),
+                   "J": J, "grad_norm": float(g.norm())},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -143,6 +190,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.workload == "adjoint":
+        adjoint_bench(a, torch, H, inputs)
+        return
     if a.calibrate_copy:
         src = torch.ones(1 << 26, dtype=torch.complex128, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
