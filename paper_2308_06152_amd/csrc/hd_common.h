@@ -174,8 +174,9 @@ hipError_t launch_receivers(const int *rec, int nrec, const cd *u, const cd *d, 
                             cd *res, cd *f, double *J, hipStream_t st);
 
 // ---- Krylov kernels ----
-// Number of partial-sum blocks used for vectors of length n.
-int krylov_blocks(size_t n);
+// Number of partial-sum blocks per vector for B vectors of length n each
+// (the launches of a batch use the same count).
+int krylov_blocks(size_t n, int B = 1);
 // part[blk][i] = sum conj(V_i) w over the block, i < m; slot m = |w|^2 if
 // with_norm.  cond != nullptr: second Gram-Schmidt pass, a no-op unless the
 // reorthogonalisation test on cond (projections, then ||w||^2 at [jcond]) fires.

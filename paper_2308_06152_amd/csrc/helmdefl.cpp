@@ -1012,7 +1012,7 @@ int vnorm_b(helm_ctx *h, const cd *v, size_t n, std::vector<double> &out, cd *si
 {
     BatchWS *W = h->bw;
     const Batch bt{W->B, dm};
-    const int nb = krylov_blocks(n);
+    const int nb = krylov_blocks(n, W->B);
     HCHK(launch_mdot(nullptr, 0, 0, v, n, W->part, 1, nullptr, 0, h->st, bt, 0, n));
     HCHK(launch_reduce(W->part, nb, 1, W->hbuf + 2 * PSTRIDE, 2, nullptr, 0, nullptr, 0, sig_out,
                        h->st, bt));
@@ -1086,7 +1086,7 @@ int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm, int nact)
     BatchWS *W = h->bw;
     const Batch bt{W->B, dm};
     const size_t n = h->L[1].n(), ld = (size_t)W->B * n;
-    const int nb = krylov_blocks(n);
+    const int nb = krylov_blocks(n, W->B);
     cd *w = W->Vc + (size_t)j1 * ld;
     cd *h1 = W->hbuf, *h2 = W->hbuf + PSTRIDE, *nr = W->hbuf + 2 * PSTRIDE;
     {
@@ -1292,7 +1292,7 @@ int arnoldi_b(helm_ctx *h, int j1, const int *dm)
     BatchWS *W = h->bw;
     const Batch bt{W->B, dm};
     const size_t n = h->L[0].n(), ld = (size_t)W->B * n;
-    const int nb = krylov_blocks(n);
+    const int nb = krylov_blocks(n, W->B);
     cd *h1 = W->hbuf, *h2 = W->hbuf + PSTRIDE, *nr = W->hbuf + 2 * PSTRIDE;
     HCHK(launch_mdot(W->V, ld, j1, W->w, n, W->part, 1, nullptr, 0, h->st, bt, n, n));
     HCHK(launch_reduce(W->part, nb, j1 + 1, h1, 0, nullptr, 0, nullptr, 0, nullptr, h->st, bt));

@@ -1291,13 +1291,17 @@ static int resident_blocks()
     return g_resident;
 }
 
-int krylov_blocks(size_t n)
+int krylov_blocks(size_t n, int B)
 {
-    const size_t res = (size_t)resident_blocks();
+    // Whole rounds of resident blocks over the B vectors together, split
+    // evenly between them; a block never takes more than 256 * KR_S entries
+    // nor fewer than 256.
+    const size_t res = (size_t)resident_blocks(), b = B > 1 ? (size_t)B : 1;
     const size_t per_round = res * 256 * KR_S;
-    const size_t rounds = (n + per_round - 1) / per_round;
-    size_t nb = res * (rounds > 0 ? rounds : 1);
-    // never more blocks than 256-entry slices of the vector
+    const size_t rounds = (n * b + per_round - 1) / per_round;
+    size_t nb = (res * (rounds > 0 ? rounds : 1) + b - 1) / b;
+    const size_t minb = (n + 256 * KR_S - 1) / (256 * KR_S);
+    if (nb < minb) nb = minb;
     const size_t maxb = (n + 255) / 256;
     if (nb > maxb) nb = maxb > 0 ? maxb : 1;
     return (int)nb;
@@ -1423,7 +1427,7 @@ hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd 
                        int with_norm, const cd *cond, int jcond, hipStream_t st, Batch bt,
                        size_t vbs, size_t wbs)
 {
-    const int nb = krylov_blocks(n);
+    const int nb = krylov_blocks(n, bt.B);
     k_mdot<<<dim3(nb, bt.B), 256, 0, st>>>(V, ld, m, w, n, krylov_chunk(n, nb), part, with_norm,
                                            cond, jcond, vbs, wbs, bt);
     HD_LAUNCH_CHECK();
@@ -1454,9 +1458,14 @@ __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *_
     const size_t base = (size_t)blockIdx.x * chunk;
     size_t end = base + chunk;
     if (end > n) end = n;
+    // acc = w - sum_i c_i V_i, started from w so that its loads overlap the
+    // first basis loads instead of waiting for the end
     cd acc[KR_S];
 #pragma unroll
-    for (int s = 0; s < KR_S; s++) acc[s] = czero();
+    for (int s = 0; s < KR_S; s++) {
+        const size_t p = base + threadIdx.x + (size_t)s * 256;
+        acc[s] = p < end ? w[p] : czero();
+    }
     int i = 0;
     for (; i + 1 < m; i += 2) {
         cd c0 = c[i], c1 = c[i + 1];
@@ -1470,10 +1479,10 @@ __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *_
             const size_t p = base + threadIdx.x + (size_t)s * 256;
             if (p < end) {
                 const cd x0 = ldnt(v0 + p), x1 = ldnt(v1 + p);
-                acc[s].x = fma(c0.x, x0.x, fma(-c0.y, x0.y, acc[s].x));
-                acc[s].y = fma(c0.x, x0.y, fma(c0.y, x0.x, acc[s].y));
-                acc[s].x = fma(c1.x, x1.x, fma(-c1.y, x1.y, acc[s].x));
-                acc[s].y = fma(c1.x, x1.y, fma(c1.y, x1.x, acc[s].y));
+                acc[s].x = fma(-c0.x, x0.x, fma(c0.y, x0.y, acc[s].x));
+                acc[s].y = fma(-c0.x, x0.y, fma(-c0.y, x0.x, acc[s].y));
+                acc[s].x = fma(-c1.x, x1.x, fma(c1.y, x1.y, acc[s].x));
+                acc[s].y = fma(-c1.x, x1.y, fma(-c1.y, x1.x, acc[s].y));
             }
         }
     }
@@ -1486,8 +1495,8 @@ __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *_
             const size_t p = base + threadIdx.x + (size_t)s * 256;
             if (p < end) {
                 const cd x0 = ldnt(v0 + p);
-                acc[s].x = fma(c0.x, x0.x, fma(-c0.y, x0.y, acc[s].x));
-                acc[s].y = fma(c0.x, x0.y, fma(c0.y, x0.x, acc[s].y));
+                acc[s].x = fma(-c0.x, x0.x, fma(c0.y, x0.y, acc[s].x));
+                acc[s].y = fma(-c0.x, x0.y, fma(-c0.y, x0.x, acc[s].y));
             }
         }
     }
@@ -1496,7 +1505,7 @@ __global__ __launch_bounds__(256) void k_mupdate(cd *__restrict__ w, const cd *_
     for (int s = 0; s < KR_S; s++) {
         const size_t p = base + threadIdx.x + (size_t)s * 256;
         if (p < end) {
-            const cd o = csub(w[p], acc[s]);
+            const cd o = acc[s];
             w[p] = o;
             nrm.x = fma(o.x, o.x, fma(o.y, o.y, nrm.x));
         }
@@ -1514,7 +1523,7 @@ hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, siz
                           const cd *cond, int jcond, const cd *sig, hipStream_t st, Batch bt,
                           size_t vbs, size_t wbs)
 {
-    const int nb = krylov_blocks(n);
+    const int nb = krylov_blocks(n, bt.B);
     k_mupdate<<<dim3(nb, bt.B), 256, 0, st>>>(w, V, ld, m, c, n, krylov_chunk(n, nb), partn,
                                               cond, jcond, sig, vbs, wbs, bt);
     HD_LAUNCH_CHECK();
