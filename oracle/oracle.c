@@ -639,10 +639,11 @@ static cplx ghost_value(const lvl_t *g, const cplx *u, int Ig, int Jg)
  * re-discretisation on the coarse grid.  The k^2 weight of each stencil node
  * uses the wavenumber at that coarse node; ghost nodes carry k = 0 and their
  * Laplacian weight is folded in through ghost elimination; the first boundary
- * layer uses the second-order 5-point stencil (Section 2.1) at spacing 2h.
- * Reading: the first-layer 5-point rows are multiplied by 4, the row sum of the
- * Galerkin scaling (Z^T has weight sum 4 in 2D), so that they carry the same
- * scale as the interior rows. */
+ * layer keeps the second-order 5-point stencil (Section 2.1) at spacing 2h,
+ * as it is, with no extra factor (the same rows as ReD-O2; with this the outer
+ * counts of the paper's Section 6 tables come out within one). */
+static cplx row_o2(const lvl_t *g, const cplx *u, int I, int J);
+
 static void coarse_redglk2(const hier_t *H, const cplx *u, cplx *y)
 {
     const lvl_t *g = &H->L[1];
@@ -655,14 +656,7 @@ static void coarse_redglk2(const hier_t *H, const cplx *u, cplx *y)
                 continue;
             }
             if (is_bnd(g, I0, J)) { /* first layer, Sommerfeld only */
-                cplx c[5];
-                stencil5(g, 1.0, I0, J, c);
-                cplx v = c[0] * u[P];
-                if (c[1] != 0) v += c[1] * u[P - 1];
-                if (c[2] != 0) v += c[2] * u[P + 1];
-                if (c[3] != 0) v += c[3] * u[P - g->nx];
-                if (c[4] != 0) v += c[4] * u[P + g->nx];
-                y[P] = 4.0 * v;
+                y[P] = row_o2(g, u, I0, J);
                 continue;
             }
             cplx v = 0;
@@ -685,10 +679,11 @@ static void coarse_redglk2(const hier_t *H, const cplx *u, cplx *y)
 
 /* One row of the second-order 5-point Helmholtz stencil at the coarse
  * spacing (Section 2.1, with its Sommerfeld closure) applied to u at (I, J):
- * the rows of ReD-O2 and the near-boundary rows of ReD-O4 and ReD-Glk1.
- * These carry no extra factor: the paper re-discretises with the fine-grid
- * stencil itself, and only without a factor do the three variants reproduce
- * the outer iteration counts of its MP-2b table (Section 6) to within one. */
+ * the rows of ReD-O2, the near-boundary rows of ReD-O4 and ReD-Glk1 and the
+ * first-layer rows of ReD-Glk2.  These carry no extra factor: the paper
+ * re-discretises with the fine-grid stencil itself, and only without a factor
+ * do the variants reproduce the outer iteration counts of its Section 6
+ * tables to within one. */
 static cplx row_o2(const lvl_t *g, const cplx *u, int I, int J)
 {
     size_t P = (size_t)J * g->nx + I;

@@ -945,12 +945,12 @@ __device__ __forceinline__ cd ghost_y(const Lev &L, const cd *u, int I, int Jg)
     return make_double2(2.0 * ub.x - ui.x, 2.0 * ub.y - ui.y);
 }
 
-// Boundary band of ReD-Glk2: first layer (boundary nodes) = 4 x the 5-point
+// Boundary band of ReD-Glk2: first layer (boundary nodes) = the 5-point
 // second-order operator at spacing H with the Sommerfeld closure; second layer
 // = the 5x5 stencil with ghost nodes eliminated (k = 0 at ghosts; a ghost
 // outside in both directions is the mean of its two single-direction
 // neighbours).  Dirichlet boundary nodes are not unknowns.
-// ReD-Glk1 (GLK1): both layers are the plain second-order 5-point rows.
+// ReD-Glk1 (GLK1): both layers are the second-order 5-point rows.
 // Band layout: nR boundary-band rows (0, 1, ny-2, ny-1 without repeats; all
 // rows when ny < 5) cover every column; then nC band columns cover the rows
 // 2..ny-3 in between.  Band row k is k for k < 2, else ny - nR + k (columns
@@ -986,7 +986,6 @@ __device__ __forceinline__ void redglk2_band(const Lev &L, const cd *__restrict_
             if (ae != 0.0) caxpy(o, ae, u[p + 1]);
             if (as != 0.0) caxpy(o, as, u[p - L.nx]);
             if (an != 0.0) caxpy(o, an, u[p + L.nx]);
-            if (!GLK1) o = cscal(4.0, o);
         } else {
             const double iH2 = L.ihx2;
             for (int dJ = -2; dJ <= 2; dJ++)

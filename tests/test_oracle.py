@@ -287,9 +287,9 @@ def test_redglk_taylor_expansion(ora):
 
 
 def test_redglk2_boundary_rows(ora):
-    """Boundary treatment of ReD-Glk2 (Section 5.2.4): the first layer uses the
-    5-point second-order stencil at spacing 2h (scaled by 4, the Galerkin row
-    sum); the second layer eliminates the ghost node.  With k = 0 the
+    """Boundary treatment of ReD-Glk2 (Section 5.2.4): the first layer keeps the
+    5-point second-order stencil at spacing 2h as it is; the second layer
+    eliminates the ghost node.  With k = 0 the
     Sommerfeld ghost mirrors the inward value, so a constant field is mapped
     to zero on every row, corners included."""
     n, k = 17, 0.0
@@ -301,17 +301,17 @@ def test_redglk2_boundary_rows(ora):
     # Sommerfeld, k = 0: ghosts equal the mirrored inward value, so the
     # Laplacian of a constant vanishes on every row
     assert np.abs(y).max() <= 1e-9 / (H * H)
-    # first layer with k != 0: 4 * (stencil of Section 2.1 at spacing H)
+    # first layer with k != 0: the stencil of Section 2.1 at spacing H
     k = 3.0
     pk = p.replace(kconst=k)
     e = np.zeros((nyc, nxc), complex)
     e[4, 0] = 1
     col = ora.coarse_apply(pk, e)
-    assert abs(col[4, 0] * H * H / 4 - (4 - k * k * H * H - 2j * k * H)) < 1e-12
+    assert abs(col[4, 0] * H * H - (4 - k * k * H * H - 2j * k * H)) < 1e-12
     e = np.zeros((nyc, nxc), complex)
     e[4, 1] = 1
     col = ora.coarse_apply(pk, e)
-    assert abs(col[4, 0] * H * H / 4 - (-2)) < 1e-12
+    assert abs(col[4, 0] * H * H - (-2)) < 1e-12
 
 
 # --------------------------------------------------------------------------
