@@ -282,8 +282,10 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
     r += (size_t)blockIdx.y * Lf.nx * Lf.ny;
     rc += (size_t)blockIdx.y * Lc.nx * Lc.ny;
     if (rs) rs += (size_t)blockIdx.y * SB;
-    // Thread (cx, cy) computes coarse node (I0+cx, J0+cy) and owns the 2 x 2
-    // fine nodes (2I+dx, 2J+dy), keeping r and then r1 there in registers.
+    // Thread t owns the fine nodes of local column 2 + (t & 63), rows
+    // 2 + 4 (t >> 6) .. + 3 (consecutive threads touch consecutive LDS
+    // entries), keeping r and then r1 there in registers, and computes coarse
+    // node (I0 + cx, J0 + cy), cx = t % 32, cy = t / 32, in the last phase.
     // One LDS tile (67 x 19, local (a, b) = fine (2*I0-2+a, 2*J0-2+b)) holds
     // x1, then is reused for r1.  The 249 halo nodes of the tile are spread
     // one per thread; those on the r1 ring (a == 1 or b == 1) also get r1.
@@ -294,6 +296,7 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
     const int I0 = (t % tiles_x) * VD_CX, J0 = (t / tiles_x) * VD_CY;
     const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
     const int cx_ = threadIdx.x % VD_CX, cy = threadIdx.x / VD_CX;
+    const int ox = 2 + (threadIdx.x & 63), oy = 2 + (threadIdx.x >> 6) * 4;  // owned column/rows
     // halo node of this thread
     int ha = -1, hb = -1;
     {
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
     C rown[4], rhalo;
 #pragma unroll
     for (int d = 0; d < 4; d++) {
-        const int fi = fi0 + 2 + 2 * cx_ + (d & 1), fj = fj0 + 2 + 2 * cy + (d >> 1);
+        const int fi = fi0 + ox, fj = fj0 + oy + d;
         const bool in = fi < Lf.nx && fj < Lf.ny && unknown(Lf, fi, fj);
         const C v = cvt<R>(r[in ? (size_t)fj * Lf.nx + fi : 0]);
         rown[d] = in ? (rs ? cscal(rsc, v) : v) : zc<R>();
@@ -334,9 +337,7 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
         return cmul(wv, rv);
     };
 #pragma unroll
-    for (int d = 0; d < 4; d++)
-        st[2 + 2 * cy + (d >> 1)][2 + 2 * cx_ + (d & 1)] =
-            x1_at(fi0 + 2 + 2 * cx_ + (d & 1), fj0 + 2 + 2 * cy + (d >> 1), rown[d]);
+    for (int d = 0; d < 4; d++) st[oy + d][ox] = x1_at(fi0 + ox, fj0 + oy + d, rown[d]);
     if (ha >= 0) st[hb][ha] = x1_at(fi0 + ha, fj0 + hb, rhalo);
     __syncthreads();
     // ---- r1 = r - M x1 at the owned nodes and the r1 ring
@@ -356,13 +357,12 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
     };
     C r1own[4], r1halo = zc<R>();
 #pragma unroll
-    for (int d = 0; d < 4; d++)
-        r1own[d] = r1_at(2 + 2 * cx_ + (d & 1), 2 + 2 * cy + (d >> 1), rown[d]);
+    for (int d = 0; d < 4; d++) r1own[d] = r1_at(ox, oy + d, rown[d]);
     const bool ring = ha >= 1 && ha <= VD_X1W - 2 && hb >= 1 && hb <= VD_X1H - 2;
     if (ring) r1halo = r1_at(ha, hb, rhalo);
     __syncthreads();
 #pragma unroll
-    for (int d = 0; d < 4; d++) st[2 + 2 * cy + (d >> 1)][2 + 2 * cx_ + (d & 1)] = r1own[d];
+    for (int d = 0; d < 4; d++) st[oy + d][ox] = r1own[d];
     if (ring) st[hb][ha] = r1halo;
     __syncthreads();
     // ---- full weighting around fine node (2I, 2J) = local (2cx+2, 2cy+2)

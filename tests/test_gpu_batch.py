@@ -111,3 +111,24 @@ def test_batched_solve_can_be_switched_off(H, ora):
         assert i1[q]["converged"] and i0[q]["converged"]
         if i1[q]["outer_iters"] == i0[q]["outer_iters"]:
             assert rel(host(x1[q]), host(x0[q])) <= 1e-8
+
+
+@pytest.mark.parametrize("kw", [dict(outer=1), dict(outer=2, coarse_mode=1, coarse_iters=20),
+                                dict(precision=1)],
+                         ids=["gcr", "left_gmres", "mixed"])
+def test_multi_rhs_paths_without_batching(H, ora, kw):
+    """GCR, left GMRES and the mixed-precision option solve several right-hand
+    sides one after another: each equals its single solve bit for bit."""
+    n, k = 65, 15.0
+    nx, ny, hx, hy = inputs.unit_square(n)
+    S, P = make_pair(H, ora, ("m", n, n, 1, "const", k, 1), coarse_mode=kw.get("coarse_mode", 2),
+                     coarse_tol=0.1, coarse_iters=kw.get("coarse_iters", 300),
+                     **{a: b for a, b in kw.items() if a not in ("coarse_mode", "coarse_iters")})
+    srcs = np.stack([inputs.point_source(nx, ny, hx, hy, 32, 32),
+                     inputs.point_source(nx, ny, hx, hy, 10, 50)])
+    xb, ib = S.solve(dev(srcs))
+    for q in range(2):
+        xs, iq = S.solve(dev(srcs[q]))
+        assert ib[q]["outer_iters"] == iq[0]["outer_iters"]
+        assert torch.equal(xb[q], xs)
+        assert ib[q]["converged"]
