@@ -1,0 +1,89 @@
+"""Parity at the benchmark's full size, in the configuration bench.py times:
+the 4097^2, k = 800 Sommerfeld workload with ReD-Glk2.  The oracle (on the
+GPU host's CPU) computes whole-grid operators at this size in seconds; the
+deflation step is compared with a fixed number of inner iterations, and the
+full solve by properties (convergence, and the true residual recomputed by the
+oracle's operator).  The batched layered workload is checked the same way."""
+import numpy as np
+import pytest
+
+from paper_2308_06152_amd import inputs
+
+from test_gpu_parity import H, dev, host, rel  # noqa: F401
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def large(H, ora):
+    w = inputs.large_plain()
+    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+                 coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol, coarse_iters=w.coarse_maxit,
+                 coarse_restart=w.coarse_restart, restart=w.restart, tol=w.tol)
+    P = ora.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+                    coarsest_nodes=S.opts.coarsest_nodes, coarse_restart=w.coarse_restart)
+    return w, S, P
+
+
+def test_full_size_operator_and_vcycle(H, ora, large):
+    w, S, P = large
+    x = inputs.random_complex((w.ny, w.nx), 201)
+    assert rel(host(S.apply(dev(x))), ora.helm_apply(P, x)) <= 1e-12
+    assert rel(host(S.vcycle(dev(x))), ora.vcycle(P, x)) <= 1e-12
+
+
+def test_full_size_coarse_operator(H, ora, large):
+    w, S, P = large
+    nxc, nyc = S.coarse_dims()
+    assert (nxc, nyc) == (2049, 2049)
+    x = inputs.random_complex((nyc, nxc), 202)
+    assert rel(host(S.coarse_apply(dev(x))), ora.coarse_apply(P, x)) <= 1e-12
+
+
+def test_full_size_adef1_fixed_inner(H, ora):
+    w = inputs.large_plain()
+    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+                 coarse_mode=H.CMODE_FIXED, coarse_iters=3, coarse_restart=w.coarse_restart)
+    P = ora.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+                    coarsest_nodes=S.opts.coarsest_nodes, coarse_mode=ora.CMODE_FIXED,
+                    coarse_iters=3, coarse_restart=w.coarse_restart)
+    v = inputs.random_complex((w.ny, w.nx), 203)
+    got = host(S.deflate(dev(v), H.DEFL_ADEF1))
+    want, it = ora.deflate_apply(P, v, ora.DEFL_ADEF1)
+    assert it == 3
+    assert rel(got, want) <= 1e-11
+
+
+def test_full_size_solve_properties(H, ora, large):
+    w, S, P = large
+    b = w.rhs()
+    x, info = S.solve(dev(b))
+    info = info[0]
+    xg = host(x)
+    r = ora.helm_apply(P, xg) - b
+    relres = np.linalg.norm(r) / np.linalg.norm(b)
+    print(f"4097^2 k=800: {info['outer_iters']} outer, {info['inner_iters_total']} inner, "
+          f"relres {relres:.3e}")
+    assert info["converged"] and relres <= 1e-6
+    assert abs(relres - info["relres"]) <= 1e-3 * relres
+    assert 8 <= info["outer_iters"] <= 12
+
+
+def test_full_size_batched_layered_properties(H, ora):
+    """The batched layered workload (2049 x 1025, 10 Hz) with 8 of its sources:
+    every right-hand side converges, with the true residual recomputed by the
+    oracle operator (variable k)."""
+    w = inputs.layered(freq=10.0, nsrc=8)
+    k = w.kfield()
+    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, k=dev(k), coarse_op=w.coarse_op,
+                 coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol, coarse_iters=w.coarse_maxit,
+                 coarse_restart=w.coarse_restart, restart=w.restart, tol=w.tol)
+    P = ora.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, k=k)
+    b = w.sources()
+    x, info = S.solve(dev(b))
+    x = host(x)
+    for q in range(len(b)):
+        r = ora.helm_apply(P, x[q]) - b[q]
+        assert info[q]["converged"]
+        assert np.linalg.norm(r) / np.linalg.norm(b[q]) <= 1e-6
