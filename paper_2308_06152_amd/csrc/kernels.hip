@@ -833,53 +833,114 @@ hipError_t launch_dresid(const Lev &Lf, const Lev &Lc, int zho, const cd *v, con
 //   the identity, H = 2h);
 //   k^2 part   = WX (x) WY applied to (k^2 u), k taken at each stencil node;
 // these reproduce the printed stencils (1/256)[...]/(2h)^2 and k^2/64^2 [...].
-// Each thread streams one column over 16 rows, keeping the x-filtered rows in
-// registers.  Boundary rows are done by redglk2_band in the same launch.
+// Each thread streams one column over RG_RPW rows, keeping the x-filtered rows
+// in registers.  Boundary rows are done by redglk2_band in the same launch.
 // ------------------------------------------------------------------------
 __constant__ double c_L1[5] = {-6.0 / 16, -8.0 / 16, 28.0 / 16, -8.0 / 16, -6.0 / 16};
 __constant__ double c_W1[5] = {1.0 / 64, 28.0 / 64, 70.0 / 64, 28.0 / 64, 1.0 / 64};
 
-constexpr int RG_TX = 64, RG_RPW = 16;  // 64 columns x (4 waves x 16 rows)
+// Interior tiling: a wave loads 64 consecutive columns and writes the 60 in
+// the middle (lanes 2..61); the west/east neighbours at distance 1 and 2 come
+// from the adjacent lanes by wave-wide DPP shifts, so each node is loaded once
+// per row it touches.  A block is 4 waves stacked over 4 x RG_RPW output rows.
+// Rows are loaded unconditionally from a clamped (valid) address and RG_AHEAD
+// rows ahead of their use, so a wave keeps several rows in flight instead of
+// waiting on each; values outside the grid or at Dirichlet nodes are then
+// replaced by zero.
+constexpr int RG_TX = 60, RG_RPW = 8, RG_AHEAD = 12;
+
+// Wave-wide lane shifts (DPP wave_shr:1 / wave_shl:1): lane i receives the
+// value of lane i-1 (west) or lane i+1 (east); lane 0 resp. 63 receives 0.
+__device__ __forceinline__ double lane_from(double v, bool west)
+{
+    const long long u = __double_as_longlong(v);
+    int lo = (int)u, hi = (int)(u >> 32);
+    if (west) {
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ cd lane_from(cd v, bool west)
+{
+    return make_double2(lane_from(v.x, west), lane_from(v.y, west));
+}
 
 template <bool RESID, bool VARK>
 __device__ __forceinline__ void redglk2_interior(const Lev &L, const cd *__restrict__ u,
                                                  const cd *__restrict__ b, cd *__restrict__ y,
-                                                 int tiles_x, int nb_int)
+                                                 int tiles_x, int nb_int, int blk)
 {
-    const int t = xcd_tile(blockIdx.x, nb_int);
-    const int I = (t % tiles_x) * RG_TX + (threadIdx.x & 63);
+    const int lane = threadIdx.x & 63;
+    const int t = xcd_tile(blk, nb_int);
+    const int I = (t % tiles_x) * RG_TX + lane;
     const int J0 = (t / tiles_x) * (4 * RG_RPW) + (threadIdx.x >> 6) * RG_RPW;
-    if (I < 2 || I > L.nx - 3) return;
-    if (J0 > L.ny - 3) return;
-    const double iH2 = L.ihx2;  // hx == hy on this path
-    const int nx = L.nx;
+    if (J0 > L.ny - 3) return;  // the whole wave: no output row here
+    const int nx = L.nx, ny = L.ny;
     const bool dir = L.bc == BC_DIR;
+    const bool colok = I < nx && !(dir && (I == 0 || I == nx - 1));
+    const int Ic = I < nx ? I : nx - 1;
+    const bool outc = lane >= 2 && lane <= 61 && I >= 2 && I <= nx - 3;
+    const double iH2 = L.ihx2;  // hx == hy on this path
+    const double kc2 = L.kc * L.kc;
+    constexpr int NR = RG_RPW + 4;
+    cd ub[NR], bb[RG_RPW];
+    double kb[NR];
+    auto load_row = [&](int q) {
+        const int jj = J0 - 2 + q;
+        const int jc = jj < 0 ? 0 : (jj >= ny ? ny - 1 : jj);
+        ub[q] = u[(size_t)jc * nx + Ic];
+        if (VARK) kb[q] = L.k[(size_t)jc * nx + Ic];
+        if (RESID && q >= 4) {
+            const int J = jj - 2;
+            bb[q - 4] = b[(size_t)(J < ny ? J : ny - 1) * nx + Ic];
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < RG_AHEAD && q < NR; q++) load_row(q);
+    // keep the loads above ahead of the arithmetic below
+    __builtin_amdgcn_sched_barrier(0);
     // rolling window of x-filtered rows: P = (LX/H^2 - k^2 WX) u  (constant k)
     //                                    or LX/H^2 u  (variable k, with R = WX (k^2 u)),
     //                                    Q = WX u / H^2
     cd P[5], Q[5], R[5];
-    const double kc2 = L.kc * L.kc;
 #pragma unroll
-    for (int q = 0; q < RG_RPW + 4; q++) {
+    for (int q = 0; q < NR; q++) {
+        if (q + RG_AHEAD < NR) load_row(q + RG_AHEAD);
         const int jj = J0 - 2 + q;
-        cd pv = czero(), qv = czero(), rv = czero();
         // Dirichlet boundary rows/columns are not unknowns: read as zero
-        const bool rowok = jj >= 0 && jj < L.ny && (!dir || (jj > 0 && jj < L.ny - 1));
-        if (rowok) {
-            const cd *row = u + (size_t)jj * nx + I;
+        const bool ok = colok && jj >= 0 && jj < ny && (!dir || (jj > 0 && jj < ny - 1));
+        // zeroing by a 0/1 factor rather than a select, so that the compiler
+        // keeps the load unconditional (a select lets it sink the load into a
+        // branch whose wait drains every row already in flight)
+        const double m = ok ? 1.0 : 0.0;
+        cd uv[5];
+        uv[2] = make_double2(ub[q].x * m, ub[q].y * m);
+        uv[1] = lane_from(uv[2], true);
+        uv[0] = lane_from(uv[1], true);
+        uv[3] = lane_from(uv[2], false);
+        uv[4] = lane_from(uv[3], false);
+        double kv[5];
+        if (VARK) {
+            kv[2] = kb[q];
+            kv[1] = lane_from(kv[2], true);
+            kv[0] = lane_from(kv[1], true);
+            kv[3] = lane_from(kv[2], false);
+            kv[4] = lane_from(kv[3], false);
+        }
+        cd pv = czero(), qv = czero(), rv = czero();
 #pragma unroll
-            for (int d = 0; d < 5; d++) {
-                const int ii = I + d - 2;
-                const cd uv = (dir && (ii == 0 || ii == nx - 1)) ? czero() : row[d - 2];
-                if (VARK) {
-                    caxpy(pv, c_L1[d] * iH2, uv);
-                    const double kk = L.k[(size_t)jj * nx + I + d - 2];
-                    caxpy(rv, c_W1[d] * kk * kk, uv);
-                } else {
-                    caxpy(pv, c_L1[d] * iH2 - kc2 * c_W1[d], uv);
-                }
-                caxpy(qv, c_W1[d] * iH2, uv);
+        for (int d = 0; d < 5; d++) {
+            if (VARK) {
+                caxpy(pv, c_L1[d] * iH2, uv[d]);
+                caxpy(rv, c_W1[d] * kv[d] * kv[d], uv[d]);
+            } else {
+                caxpy(pv, c_L1[d] * iH2 - kc2 * c_W1[d], uv[d]);
             }
+            caxpy(qv, c_W1[d] * iH2, uv[d]);
         }
 #pragma unroll
         for (int d = 0; d < 4; d++) {
@@ -892,7 +953,7 @@ __device__ __forceinline__ void redglk2_interior(const Lev &L, const cd *__restr
         if (VARK) R[4] = rv;
         if (q >= 4) {
             const int J = jj - 2;
-            if (J >= 2 && J <= L.ny - 3) {
+            if (outc && J >= 2 && J <= ny - 3) {
                 cd o = czero();
 #pragma unroll
                 for (int d = 0; d < 5; d++) {
@@ -901,7 +962,7 @@ __device__ __forceinline__ void redglk2_interior(const Lev &L, const cd *__restr
                     if (VARK) caxpy(o, -c_W1[d], R[d]);
                 }
                 const size_t p = (size_t)J * nx + I;
-                if (RESID) o = csub(b[p], o);
+                if (RESID) o = csub(bb[q - 4], o);
                 y[p] = o;
             }
         }
@@ -1012,13 +1073,16 @@ __device__ __forceinline__ void redglk2_band(const Lev &L, const cd *__restrict_
     y[p] = o;
 }
 
-// One launch for the whole coarse operator: blocks [0, nb_int) do interior
-// tiles, the blocks after them the boundary band, so both run concurrently.
+// One launch for the whole coarse operator: blocks [0, nb_band) do the
+// boundary band, the blocks after them the interior tiles, so both run
+// concurrently.  The band goes first: its nodes take long dependent chains of
+// reads, which then overlap the interior instead of trailing it.  nb_band is a
+// multiple of 8, so block ids keep their XCD in the interior's tile map.
 template <bool RESID, bool VARK, bool GLK1>
 __global__ __launch_bounds__(256) void k_redglk2(Lev L, const cd *__restrict__ u,
                                                  const cd *__restrict__ b, cd *__restrict__ y,
-                                                 int tiles_x, int nb_int, int nR, int nC,
-                                                 int count, Batch bt)
+                                                 int tiles_x, int nb_int, int nb_band, int nR,
+                                                 int nC, int count, Batch bt)
 {
     if (skip_rhs(bt)) return;
     {
@@ -1027,10 +1091,10 @@ __global__ __launch_bounds__(256) void k_redglk2(Lev L, const cd *__restrict__ u
         if (RESID) b += off;
         y += off;
     }
-    if ((int)blockIdx.x < nb_int)
-        redglk2_interior<RESID, VARK>(L, u, b, y, tiles_x, nb_int);
+    if ((int)blockIdx.x < nb_band)
+        redglk2_band<RESID, GLK1>(L, u, b, y, nR, nC, count, blockIdx.x);
     else
-        redglk2_band<RESID, GLK1>(L, u, b, y, nR, nC, count, blockIdx.x - nb_int);
+        redglk2_interior<RESID, VARK>(L, u, b, y, tiles_x, nb_int, blockIdx.x - nb_band);
 }
 
 template <bool GLK1>
@@ -1038,29 +1102,30 @@ static hipError_t redglk_t(const Lev &L, const cd *x, const cd *b, cd *y, hipStr
 {
     int tx = 0, nb_int = 0;
     if (L.nx >= 5 && L.ny >= 5) {
-        tx = cdiv(L.nx, RG_TX);
+        tx = cdiv(L.nx - 4, RG_TX);
         nb_int = tx * cdiv(L.ny, 4 * RG_RPW);
     }
     // band: rows {0,1,ny-2,ny-1} and columns {0,1,nx-2,nx-1} without repeats
     const int nR = L.ny < 4 ? L.ny : 4, nC = L.nx < 4 ? L.nx : 4;
     const int inner_rows = L.ny - nR;  // rows 2..ny-3 when ny >= 5, else 0
     const int count = nR * L.nx + nC * inner_rows;
-    const dim3 g(nb_int + cdiv(count, 256), bt.B);
+    const int nb_band = cdiv(cdiv(count, 256), 8) * 8;
+    const dim3 g(nb_band + nb_int, bt.B);
+#define RG_LAUNCH(RES, VK)                                                                   \
+    k_redglk2<RES, VK, GLK1><<<g, 256, 0, st>>>(L, x, b, y, tx, nb_int, nb_band, nR, nC, count, \
+                                                bt)
     if (L.k) {
         if (b)
-            k_redglk2<true, true, GLK1><<<g, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count,
-                                                          bt);
+            RG_LAUNCH(true, true);
         else
-            k_redglk2<false, true, GLK1><<<g, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count,
-                                                           bt);
+            RG_LAUNCH(false, true);
     } else {
         if (b)
-            k_redglk2<true, false, GLK1><<<g, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC, count,
-                                                           bt);
+            RG_LAUNCH(true, false);
         else
-            k_redglk2<false, false, GLK1><<<g, 256, 0, st>>>(L, x, b, y, tx, nb_int, nR, nC,
-                                                            count, bt);
+            RG_LAUNCH(false, false);
     }
+#undef RG_LAUNCH
     HD_LAUNCH_CHECK();
 }
 
