@@ -71,11 +71,11 @@ __host__ __device__ inline bool unknown(const Lev &L, int i, int j)
 // node beyond a boundary node is eliminated (u_ghost = u_inward + 2ikh u_bnd),
 // adding -2ik/h to ap and doubling the inward coupling, per direction.
 // Dirichlet: boundary nodes are not unknowns (returns false); couplings to
-// them are dropped.  (i,j) must lie inside the grid.
-__host__ __device__ inline bool coef5(const Lev &L, cd s, int i, int j, cd &ap, double &aw,
-                                      double &ae, double &as, double &an)
+// them are dropped.  (i,j) must lie inside the grid; k is the wavenumber
+// there (coef5 reads it from the level).
+__host__ __device__ inline bool coef5k(const Lev &L, cd s, int i, int j, double k, cd &ap,
+                                       double &aw, double &ae, double &as, double &an)
 {
-    const double k = kat(L, i, j);
     const double k2 = k * k;
     ap = make_double2(2.0 * L.ihx2 + 2.0 * L.ihy2 - s.x * k2, -s.y * k2);
     aw = -L.ihx2;
@@ -111,6 +111,12 @@ __host__ __device__ inline bool coef5(const Lev &L, cd s, int i, int j, cd &ap, 
     if (j == 1) as = 0.0;
     if (j == L.ny - 2) an = 0.0;
     return true;
+}
+
+__host__ __device__ inline bool coef5(const Lev &L, cd s, int i, int j, cd &ap, double &aw,
+                                      double &ae, double &as, double &an)
+{
+    return coef5k(L, s, i, j, kat(L, i, j), ap, aw, ae, as, an);
 }
 
 // ---- launch wrappers (kernels.hip); all return the launch's hipError_t ----

@@ -70,6 +70,33 @@ template <class R> __device__ __forceinline__ cx<R> zc() { return mkc<R>((R)0, (
 template <class R> __device__ __forceinline__ cx<R> cvt(cd a) { return mkc<R>((R)a.x, (R)a.y); }
 template <class R> __device__ __forceinline__ cx<R> cvt(cf a) { return mkc<R>((R)a.x, (R)a.y); }
 
+// Wave-wide lane shifts (DPP wave_shr:1 / wave_shl:1): lane i receives the
+// value of lane i-1 (west) or lane i+1 (east); lane 0 resp. 63 receives 0.
+// Every lane of the wave must be active.
+__device__ __forceinline__ int lane_from(int v, bool west)
+{
+    return west ? __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false)
+                : __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float lane_from(float v, bool west)
+{
+    return __int_as_float(lane_from(__float_as_int(v), west));
+}
+__device__ __forceinline__ double lane_from(double v, bool west)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = lane_from((int)u, west), hi = lane_from((int)(u >> 32), west);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ cd lane_from(cd v, bool west)
+{
+    return make_double2(lane_from(v.x, west), lane_from(v.y, west));
+}
+__device__ __forceinline__ cf lane_from(cf v, bool west)
+{
+    return make_float2(lane_from(v.x, west), lane_from(v.y, west));
+}
+
 // Map hardware block id to a logical tile id so that each of the 8 XCDs
 // (which receive block ids round-robin) works on a contiguous range of tiles.
 __device__ __forceinline__ int xcd_tile(int b, int nb)
@@ -226,12 +253,13 @@ Smooth<R> smooth_consts(const Lev &L, cd s, double omega)
     return c;
 }
 
-// Coefficients of node (i,j) (inside the grid) in precision R.  Returns false
-// for a non-unknown node.  winv = omega / ap.
+// Coefficients of node (i,j) (inside the grid) in precision R, k being the
+// wavenumber there (read only on variable-k levels and at boundary nodes).
+// Returns false for a non-unknown node.  winv = omega / ap.
 template <bool VARK, class R>
-__device__ __forceinline__ bool node_coef(const Lev &L, cd s, double omega, const Smooth<R> &c,
-                                          int i, int j, cx<R> &ap, cx<R> &winv, R &aw, R &ae,
-                                          R &as, R &an)
+__device__ __forceinline__ bool node_coef_k(const Lev &L, cd s, double omega, const Smooth<R> &c,
+                                            int i, int j, double k, cx<R> &ap, cx<R> &winv,
+                                            R &aw, R &ae, R &as, R &an)
 {
     const bool edge = i == 0 || j == 0 || i == L.nx - 1 || j == L.ny - 1;
     if (!VARK && !edge) {
@@ -242,12 +270,12 @@ __device__ __forceinline__ bool node_coef(const Lev &L, cd s, double omega, cons
         return true;
     }
     if constexpr (std::is_same<R, double>::value) {
-        if (!coef5(L, s, i, j, ap, aw, ae, as, an)) return false;
+        if (!coef5k(L, s, i, j, k, ap, aw, ae, as, an)) return false;
         winv = cscal(omega, cinv(ap));
     } else {
         cd apd;
         double awd, aed, asd, and_;
-        if (!coef5(L, s, i, j, apd, awd, aed, asd, and_)) return false;
+        if (!coef5k(L, s, i, j, k, apd, awd, aed, asd, and_)) return false;
         ap = cvt<R>(apd);
         winv = cvt<R>(cscal(omega, cinv(apd)));
         aw = (R)awd;
@@ -256,6 +284,16 @@ __device__ __forceinline__ bool node_coef(const Lev &L, cd s, double omega, cons
         an = (R)and_;
     }
     return true;
+}
+
+template <bool VARK, class R>
+__device__ __forceinline__ bool node_coef(const Lev &L, cd s, double omega, const Smooth<R> &c,
+                                          int i, int j, cx<R> &ap, cx<R> &winv, R &aw, R &ae,
+                                          R &as, R &an)
+{
+    // a constant-k level (VARK false) has no k array: no load
+    const double k = VARK ? kat(L, i, j) : L.kc;
+    return node_coef_k<VARK, R>(L, s, omega, c, i, j, k, ap, winv, aw, ae, as, an);
 }
 
 // ------------------------------------------------------------------------
@@ -313,40 +351,57 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
     }
     // ---- global loads (unconditional, from a valid address); r is taken
     // as 0 at non-unknown nodes (Dirichlet boundary) and outside the grid
+    // (zeroing by a 0/1 factor rather than a select keeps the loads
+    // unconditional: a select lets the compiler sink each load into a branch
+    // that waits for it before the next one is issued)
+    // On a variable-k level the wavenumber of the same nodes is loaded with r
+    // (the coefficients of a node are used only where it is an unknown).
     C rown[4], rhalo;
+    R mown[4], mhalo;
+    double kown[4], khalo = 0.0;
 #pragma unroll
     for (int d = 0; d < 4; d++) {
         const int fi = fi0 + ox, fj = fj0 + oy + d;
         const bool in = fi < Lf.nx && fj < Lf.ny && unknown(Lf, fi, fj);
-        const C v = cvt<R>(r[in ? (size_t)fj * Lf.nx + fi : 0]);
-        rown[d] = in ? (rs ? cscal(rsc, v) : v) : zc<R>();
+        const size_t p = in ? (size_t)fj * Lf.nx + fi : 0;
+        rown[d] = cvt<R>(r[p]);
+        mown[d] = in ? (R)1 : (R)0;
+        kown[d] = VARK ? Lf.k[p] : Lf.kc;
     }
     {
         const int fi = fi0 + ha, fj = fj0 + hb;
         const bool in = ha >= 0 && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny &&
                         unknown(Lf, fi, fj);
-        const C v = cvt<R>(r[in ? (size_t)fj * Lf.nx + fi : 0]);
-        rhalo = in ? (rs ? cscal(rsc, v) : v) : zc<R>();
+        const size_t p = in ? (size_t)fj * Lf.nx + fi : 0;
+        rhalo = cvt<R>(r[p]);
+        mhalo = in ? (R)1 : (R)0;
+        if (VARK) khalo = Lf.k[p];
     }
-    auto x1_at = [&](int fi, int fj, C rv) -> C {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int d = 0; d < 4; d++) rown[d] = cscal(mown[d], rs ? cscal(rsc, rown[d]) : rown[d]);
+    rhalo = cscal(mhalo, rs ? cscal(rsc, rhalo) : rhalo);
+    if (!VARK) khalo = Lf.kc;
+    auto x1_at = [&](int fi, int fj, C rv, double kv) -> C {
         C ap, wv;
         R aw, ae, as, an;
         if (fi < 0 || fi >= Lf.nx || fj < 0 || fj >= Lf.ny ||
-            !node_coef<VARK, R>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
+            !node_coef_k<VARK, R>(Lf, s, omega, c, fi, fj, kv, ap, wv, aw, ae, as, an))
             return zc<R>();
         return cmul(wv, rv);
     };
 #pragma unroll
-    for (int d = 0; d < 4; d++) st[oy + d][ox] = x1_at(fi0 + ox, fj0 + oy + d, rown[d]);
-    if (ha >= 0) st[hb][ha] = x1_at(fi0 + ha, fj0 + hb, rhalo);
+    for (int d = 0; d < 4; d++)
+        st[oy + d][ox] = x1_at(fi0 + ox, fj0 + oy + d, rown[d], kown[d]);
+    if (ha >= 0) st[hb][ha] = x1_at(fi0 + ha, fj0 + hb, rhalo, khalo);
     __syncthreads();
     // ---- r1 = r - M x1 at the owned nodes and the r1 ring
-    auto r1_at = [&](int a, int b, C rv) -> C {
+    auto r1_at = [&](int a, int b, C rv, double kv) -> C {
         const int fi = fi0 + a, fj = fj0 + b;
         C ap, wv;
         R aw, ae, as, an;
         if (fi < 0 || fi >= Lf.nx || fj < 0 || fj >= Lf.ny ||
-            !node_coef<VARK, R>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
+            !node_coef_k<VARK, R>(Lf, s, omega, c, fi, fj, kv, ap, wv, aw, ae, as, an))
             return zc<R>();
         C m = cmul(ap, st[b][a]);
         caxpy(m, aw, st[b][a - 1]);
@@ -357,9 +412,9 @@ __global__ __launch_bounds__(256) void k_vc_down(Lev Lf, Lev Lc, cd s, double om
     };
     C r1own[4], r1halo = zc<R>();
 #pragma unroll
-    for (int d = 0; d < 4; d++) r1own[d] = r1_at(ox, oy + d, rown[d]);
+    for (int d = 0; d < 4; d++) r1own[d] = r1_at(ox, oy + d, rown[d], kown[d]);
     const bool ring = ha >= 1 && ha <= VD_X1W - 2 && hb >= 1 && hb <= VD_X1H - 2;
-    if (ring) r1halo = r1_at(ha, hb, rhalo);
+    if (ring) r1halo = r1_at(ha, hb, rhalo, khalo);
     __syncthreads();
 #pragma unroll
     for (int d = 0; d < 4; d++) st[oy + d][ox] = r1own[d];
@@ -478,30 +533,56 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
         }
     }
     // ---- all global loads first (unconditional, from a valid address)
+    // (zeroing by a 0/1 factor rather than a select keeps the loads
+    // unconditional, see k_vc_down)
+    // (on a variable-k level the wavenumber of the same nodes comes with r;
+    // when accumulating, the old output of the owned nodes too)
     C el[NKC], rown[4], rhalo;
+    R mel[NKC], mown[4], mhalo;
+    double kown[4], khalo = 0.0;
+    cx<RO> oold[4];
 #pragma unroll
     for (int kq = 0; kq < NKC; kq++) {
         const int q = threadIdx.x + 256 * kq;
         const int I = ci0 + q % VU_CW, J = cj0 + q / VU_CW;
         const bool in = q < NC && I >= 0 && I < Lc.nx && J >= 0 && J < Lc.ny && unknown(Lc, I, J);
-        const C v = ec[in ? (size_t)J * Lc.nx + I : 0];
-        el[kq] = in ? v : zc<R>();
+        el[kq] = ec[in ? (size_t)J * Lc.nx + I : 0];
+        mel[kq] = in ? (R)1 : (R)0;
     }
     const int i = i0 + tx;
 #pragma unroll
     for (int rr = 0; rr < 4; rr++) {
         const int j = j0 + 4 * ty + rr;
         const bool in = i < Lf.nx && j < Lf.ny && unknown(Lf, i, j);
-        const C v = cvt<R>(r[in ? (size_t)j * Lf.nx + i : 0]);
-        rown[rr] = in ? (rs ? cscal(rsc, v) : v) : zc<R>();
+        const size_t p = in ? (size_t)j * Lf.nx + i : 0;
+        rown[rr] = cvt<R>(r[p]);
+        mown[rr] = in ? (R)1 : (R)0;
+        kown[rr] = VARK ? Lf.k[p] : Lf.kc;
+    }
+    if (accumulate) {
+#pragma unroll
+        for (int rr = 0; rr < 4; rr++) {
+            const int j = j0 + 4 * ty + rr;
+            oold[rr] = out[i < Lf.nx && j < Lf.ny ? (size_t)j * Lf.nx + i : 0];
+        }
     }
     {
         const int fi = i0 - 1 + ha, fj = j0 - 1 + hb;
         const bool in = ha >= 0 && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny &&
                         unknown(Lf, fi, fj);
-        const C v = cvt<R>(r[in ? (size_t)fj * Lf.nx + fi : 0]);
-        rhalo = in ? (rs ? cscal(rsc, v) : v) : zc<R>();
+        const size_t p = in ? (size_t)fj * Lf.nx + fi : 0;
+        rhalo = cvt<R>(r[p]);
+        mhalo = in ? (R)1 : (R)0;
+        if (VARK) khalo = Lf.k[p];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    if (!VARK) khalo = Lf.kc;
+#pragma unroll
+    for (int kq = 0; kq < NKC; kq++) el[kq] = cscal(mel[kq], el[kq]);
+#pragma unroll
+    for (int rr = 0; rr < 4; rr++)
+        rown[rr] = cscal(mown[rr], rs ? cscal(rsc, rown[rr]) : rown[rr]);
+    rhalo = cscal(mhalo, rs ? cscal(rsc, rhalo) : rhalo);
 #pragma unroll
     for (int kq = 0; kq < NKC; kq++) {
         const int q = threadIdx.x + 256 * kq;
@@ -509,11 +590,11 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
     }
     __syncthreads();
     // ---- x2 = omega D^-1 r + P ec at the owned nodes and the halo node
-    auto x2_at = [&](int fi, int fj, C rv) -> C {
+    auto x2_at = [&](int fi, int fj, C rv, double kv) -> C {
         C ap, wv;
         R aw, ae, as, an;
         if (fi < 0 || fi >= Lf.nx || fj < 0 || fj >= Lf.ny ||
-            !node_coef<VARK, R>(Lf, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
+            !node_coef_k<VARK, R>(Lf, s, omega, c, fi, fj, kv, ap, wv, aw, ae, as, an))
             return zc<R>();
         // bilinear interpolation from the coarse tile: coarse node
         // (fi >> 1, fj >> 1) sits at se[(fj >> 1) - cj0][(fi >> 1) - ci0]
@@ -530,9 +611,9 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
 #pragma unroll
     for (int rr = 0; rr < 4; rr++) {
         const int jl = 4 * ty + rr;
-        sx2[jl + 1][tx + 1] = x2_at(i, j0 + jl, rown[rr]);
+        sx2[jl + 1][tx + 1] = x2_at(i, j0 + jl, rown[rr], kown[rr]);
     }
-    if (ha >= 0) sx2[hb][ha] = x2_at(i0 - 1 + ha, j0 - 1 + hb, rhalo);
+    if (ha >= 0) sx2[hb][ha] = x2_at(i0 - 1 + ha, j0 - 1 + hb, rhalo, khalo);
     __syncthreads();
     // ---- post-smoothing at the owned nodes
     if (i >= Lf.nx) return;
@@ -546,7 +627,7 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
         C ap, wv;
         R aw, ae, as, an;
         cx<RO> v = zc<RO>();
-        if (node_coef<VARK, R>(Lf, s, omega, c, i, j, ap, wv, aw, ae, as, an)) {
+        if (node_coef_k<VARK, R>(Lf, s, omega, c, i, j, kown[rr], ap, wv, aw, ae, as, an)) {
             C m = cmul(ap, sx2[bb][a]);
             caxpy(m, aw, sx2[bb][a - 1]);
             caxpy(m, ae, sx2[bb][a + 1]);
@@ -555,7 +636,7 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
             v = cvt<RO>(cadd(sx2[bb][a], cmul(wv, csub(rown[rr], m))));
             if (v2) v = cadd(v, cvt<RO>(prolong_at(Lc, v2, i, j, zho)));
         }
-        if (accumulate) v = cadd(v, out[p]);
+        if (accumulate) v = cadd(v, oold[rr]);
         out[p] = v;
     }
 }
@@ -848,26 +929,6 @@ __constant__ double c_W1[5] = {1.0 / 64, 28.0 / 64, 70.0 / 64, 28.0 / 64, 1.0 / 
 // waiting on each; values outside the grid or at Dirichlet nodes are then
 // replaced by zero.
 constexpr int RG_TX = 60, RG_RPW = 8, RG_AHEAD = 12;
-
-// Wave-wide lane shifts (DPP wave_shr:1 / wave_shl:1): lane i receives the
-// value of lane i-1 (west) or lane i+1 (east); lane 0 resp. 63 receives 0.
-__device__ __forceinline__ double lane_from(double v, bool west)
-{
-    const long long u = __double_as_longlong(v);
-    int lo = (int)u, hi = (int)(u >> 32);
-    if (west) {
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
-    } else {
-        lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);
-        hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
-    }
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ cd lane_from(cd v, bool west)
-{
-    return make_double2(lane_from(v.x, west), lane_from(v.y, west));
-}
 
 template <bool RESID, bool VARK>
 __device__ __forceinline__ void redglk2_interior(const Lev &L, const cd *__restrict__ u,
