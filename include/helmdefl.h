@@ -101,14 +101,17 @@ typedef struct {
                                 (default 1089 = 33 x 33; 0 = down to 3 x 3;
                                 at most 2048) */
     int precision;           /* HELM_PREC_FP64 (default): everything in FP64.
-                                HELM_PREC_MIXED: the fine-grid CSLP V-cycle
+                                HELM_PREC_MIXED: (1) the fine-grid CSLP V-cycle
                                 (cslp_vcycle, and M^{-1} inside A-DEF1) runs in
                                 complex64 on every level: it reads r in FP64,
-                                stores the levels in FP32 and writes z in FP64.
-                                The Krylov methods, A_h, the deflation (with its
-                                coarse GMRES and that solve's own V-cycle) and
-                                the residual test stay FP64; FGMRES absorbs the
-                                perturbed preconditioner (Section 5.2). */
+                                stores the levels in FP32 and writes z in FP64;
+                                (2) the coarse GMRES stores its Krylov basis in
+                                complex64 (when its V-cycle has a level below
+                                level 1), with A_2h, that V-cycle, the products
+                                and the updates in FP64.  The outer Krylov
+                                method, A_h, Z, Z^T and the residual test stay
+                                FP64; FGMRES absorbs the perturbed
+                                preconditioner (Section 5.2). */
     int outer;               /* HELM_OUTER_* (default HELM_OUTER_FGMRES)       */
     int batch;               /* nrhs > 1 with the FP64 path: 1 (default) = all
                                 right-hand sides in one batched pass (one launch

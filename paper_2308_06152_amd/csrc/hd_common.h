@@ -147,6 +147,13 @@ hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const 
                         hipStream_t st);
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
                         const cf *ec, cf *out, hipStream_t st);
+// The top level of a cycle whose right-hand side is a complex64 vector (the
+// mixed-precision inner Krylov basis), scaled by rs[0].x, with FP64 arithmetic
+// and FP64 levels below.
+hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
+                          const cd *rs, cd *rc, hipStream_t st);
+hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
+                        const cd *rs, const cd *ec, cd *out, int accumulate, hipStream_t st);
 // x = Minv r on the coarsest level (dense inverse, n x n, row major).
 hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st,
                            Batch bt = Batch{});
@@ -180,9 +187,13 @@ hipError_t launch_receivers(const int *rec, int nrec, const cd *u, const cd *d, 
                             cd *res, cd *f, double *J, hipStream_t st);
 
 // ---- Krylov kernels ----
-// Number of partial-sum blocks per vector for B vectors of length n each
-// (the launches of a batch use the same count).
-int krylov_blocks(size_t n, int B = 1);
+// Number of partial-sum blocks per vector that the Krylov kernel `kind` uses
+// for B vectors of length n each (every launch of that kernel, and the
+// reduction of its partial sums, use this count); the partial-sum buffers
+// need krylov_blocks_max blocks per vector.
+enum { KB_DOT = 0, KB_UPDATE = 1, KB_DOT32 = 2, KB_UPDATE32 = 3, KB_NKINDS = 4 };
+int krylov_blocks(size_t n, int B = 1, int kind = KB_DOT);
+int krylov_blocks_max(size_t n, int B = 1);
 // part[blk][i] = sum conj(V_i) w over the block, i < m; slot m = |w|^2 if
 // with_norm.  cond != nullptr: second Gram-Schmidt pass, a no-op unless the
 // reorthogonalisation test on cond (projections, then ||w||^2 at [jcond]) fires.
@@ -195,6 +206,19 @@ hipError_t launch_mdot(const cd *V, size_t ld, int m, const cd *w, size_t n, cd 
 hipError_t launch_mupdate(cd *w, const cd *V, size_t ld, int m, const cd *c, size_t n, cd *partn,
                           const cd *cond, int jcond, const cd *sig, hipStream_t st,
                           Batch bt = Batch{}, size_t vbs = 0, size_t wbs = 0);
+// The same two kernels on a complex64 basis V (mixed precision): products and
+// updates are formed in FP64; w is read as complex128 or complex64, and the
+// update writes complex64 (in place, or from a complex128 w into wout), with
+// partn the norm of the stored entries.
+hipError_t launch_mdot32(const cf *V, size_t ld, int m, const cd *w, size_t n, cd *part,
+                         int with_norm, const cd *cond, int jcond, hipStream_t st);
+hipError_t launch_mdot32(const cf *V, size_t ld, int m, const cf *w, size_t n, cd *part,
+                         int with_norm, const cd *cond, int jcond, hipStream_t st);
+hipError_t launch_mupdate32(const cd *win, cf *wout, const cf *V, size_t ld, int m, const cd *c,
+                            size_t n, cd *partn, const cd *cond, int jcond, const cd *sig,
+                            hipStream_t st);
+hipError_t launch_mupdate32(cf *w, const cf *V, size_t ld, int m, const cd *c, size_t n,
+                            cd *partn, const cd *cond, int jcond, const cd *sig, hipStream_t st);
 // out[i] (=|+=) sum_blk part[blk][i], i < m (mode 0: times sig[i] for
 // i < nsig); mode 2: out[0] = (sqrt(sum re), 0) and sig_out[0] = its
 // reciprocal.  cond: as above; writes zeros when the second pass is skipped.
@@ -208,6 +232,9 @@ hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t
 hipError_t launch_lincomb(const cd *V, size_t ld, int m, const cd *y, cd *out, size_t n,
                           int accumulate, hipStream_t st, Batch bt = Batch{}, size_t vbs = 0,
                           size_t obs = 0);
+// out (+)= sum_i y_i V_i for a complex64 basis (FP64 sums).
+hipError_t launch_lincomb32(const cf *V, size_t ld, int m, const cd *y, cd *out, size_t n,
+                            int accumulate, hipStream_t st);
 // p[0..n) = 0.
 hipError_t launch_zero(cd *p, size_t n, hipStream_t st);
 // out = in with the non-unknown (Dirichlet boundary) entries set to zero.

@@ -149,6 +149,10 @@ struct helm_ctx {
     // inner GMRES
     int mc = 0;
     cd *Vc = nullptr, *wc = nullptr, *zc_ = nullptr, *xin = nullptr;
+    // mixed precision: the inner basis in complex64 (FP64 A_2h output in wtmp)
+    bool basis32 = false;
+    cf *Vc32 = nullptr;
+    cd *wtmp = nullptr;
     // reductions
     cd *part = nullptr, *partn = nullptr;
     int part_blocks = 0;
@@ -286,7 +290,7 @@ int vnorm(helm_ctx *h, const cd *v, size_t n, double *out, cd *sig_out = nullptr
 int arnoldi_step(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col, double *hn,
                  int lev)
 {
-    const int nb = krylov_blocks(n);
+    const int nb = krylov_blocks(n), nbu = krylov_blocks(n, 1, KB_UPDATE);
     cd *h1 = h->hbuf, *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
     {
         Timed tm(h, HELM_K_DOT, lev, 16.0 * (j1 + 1) * n);
@@ -301,7 +305,7 @@ int arnoldi_step(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col
     HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
     HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, nullptr, 0, nullptr, h->st));
     HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, nullptr, h->st));
-    HCHK(launch_reduce(h->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, nullptr, h->st));
+    HCHK(launch_reduce(h->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, nullptr, h->st));
     HCHK(launch_scale(w, nr, V + (size_t)j1 * ld, n, h->st));
     HCHK(hipMemcpyAsync(h->hpin, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd), hipMemcpyDeviceToHost,
                         h->st));
@@ -325,7 +329,7 @@ int arnoldi_step(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col
 // is recorded.  arnoldi_finish() waits for that event.
 int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int lev, int slot)
 {
-    const int nb = krylov_blocks(n);
+    const int nb = krylov_blocks(n), nbu = krylov_blocks(n, 1, KB_UPDATE);
     cd *w = V + (size_t)j1 * ld;
     cd *h1 = h->hbuf, *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
     {
@@ -340,7 +344,7 @@ int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int le
     HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
     HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
     HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
-    HCHK(launch_reduce(h->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, h->sig + j1, h->st));
+    HCHK(launch_reduce(h->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, h->sig + j1, h->st));
     HCHK(hipMemcpyAsync(h->hpin + slot * HBUF, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd),
                         hipMemcpyDeviceToHost, h->st));
     HCHK(hipEventRecord(h->ev_slot[slot], h->st));
@@ -458,6 +462,32 @@ int vcycle(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2
     return HELM_OK;
 }
 
+// z = V-cycle(rs[0].x r) from level 1 for a complex64 r (an entry of the
+// mixed-precision inner basis): the top level reads r in complex64, the
+// arithmetic and the levels below are FP64.  Needs a level below level 1.
+int vcycle32(helm_ctx *h, const cf *r, cd *z, const cd *rs)
+{
+    const int Lc = h->nlev - 1;
+    {
+        Timed tm(h, HELM_K_VC_DOWN, 1, 8.0 * h->L[1].n() + 16.0 * h->L[2].n());
+        HCHK(launch_vc_down(h->lev(1), h->lev(2), h->shift, h->o.omega, r, rs, h->L[2].r, h->st));
+    }
+    for (int l = 2; l < Lc; l++) {
+        Timed tm(h, HELM_K_VC_DOWN, l, 16.0 * h->L[l].n() + 16.0 * h->L[l + 1].n());
+        HCHK(launch_vc_down(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, h->L[l].r, nullptr,
+                            h->L[l + 1].r, h->st));
+    }
+    HCHK(launch_coarsest(h->ncoarsest, h->cinv, h->L[Lc].r, h->L[Lc].x, h->st));
+    for (int l = Lc - 1; l >= 2; l--) {
+        Timed tm(h, HELM_K_VC_UP, l, 32.0 * h->L[l].n() + 16.0 * h->L[l + 1].n());
+        HCHK(launch_vc_up(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, h->L[l].r, nullptr,
+                          h->L[l + 1].x, h->L[l].x, 0, nullptr, h->zho, h->st));
+    }
+    Timed tm(h, HELM_K_VC_UP, 1, 24.0 * h->L[1].n() + 16.0 * h->L[2].n());
+    HCHK(launch_vc_up(h->lev(1), h->lev(2), h->shift, h->o.omega, r, rs, h->L[2].x, z, 0, h->st));
+    return HELM_OK;
+}
+
 // y = A_2h x  or  y = b - A_2h x
 int coarse_apply(helm_ctx *h, const cd *x, const cd *b, cd *y)
 {
@@ -490,6 +520,53 @@ int inner_step_enqueue(helm_ctx *h, int j, int slot)
     return arnoldi_lazy_enqueue(h, h->Vc, nc, j + 1, nc, 1, slot);
 }
 
+// The same step on the complex64 basis (mixed precision): A_2h z is formed
+// in FP64 in wtmp; the first Gram-Schmidt pass reads it and writes the
+// orthogonalised vector, rounded, into basis slot j1; a second pass (when
+// needed) works in place on that slot.  Products and norms are FP64.
+int arnoldi_lazy_enqueue32(helm_ctx *h, size_t n, int j1, int slot)
+{
+    const int nb = krylov_blocks(n, 1, KB_DOT32), nbu = krylov_blocks(n, 1, KB_UPDATE32);
+    const size_t ld = n;
+    const cf *V = h->Vc32;
+    cf *w = h->Vc32 + (size_t)j1 * ld;
+    cd *h1 = h->hbuf, *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
+    {
+        Timed tm(h, HELM_K_DOT, 1, 8.0 * j1 * n + 16.0 * n);
+        HCHK(launch_mdot32(V, ld, j1, h->wtmp, n, h->part, 1, nullptr, 0, h->st));
+    }
+    HCHK(launch_reduce(h->part, nb, j1 + 1, h1, 0, nullptr, 0, h->sig, j1, nullptr, h->st));
+    {
+        Timed tm(h, HELM_K_UPDATE, 1, 8.0 * j1 * n + 24.0 * n);
+        HCHK(launch_mupdate32(h->wtmp, w, V, ld, j1, h1, n, h->partn, nullptr, 0, h->sig, h->st));
+    }
+    HCHK(launch_mdot32(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
+    HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
+    HCHK(launch_mupdate32(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
+    HCHK(launch_reduce(h->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, h->sig + j1, h->st));
+    HCHK(hipMemcpyAsync(h->hpin + slot * HBUF, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd),
+                        hipMemcpyDeviceToHost, h->st));
+    HCHK(hipEventRecord(h->ev_slot[slot], h->st));
+    return HELM_OK;
+}
+
+int inner_step_enqueue32(helm_ctx *h, int j, int slot)
+{
+    const size_t nc = h->L[1].n();
+    RCHK(vcycle32(h, h->Vc32 + (size_t)j * nc, h->zc_, h->sig + j));
+    RCHK(coarse_apply(h, h->zc_, nullptr, h->wtmp));
+    return arnoldi_lazy_enqueue32(h, nc, j + 1, slot);
+}
+
+// Basis slot 0 (complex64) = u (FP64), rounded.
+int basis32_set0(helm_ctx *h, const cd *u)
+{
+    const size_t nc = h->L[1].n();
+    HCHK(launch_mupdate32(u, h->Vc32, h->Vc32, nc, 0, h->hbuf, nc, h->partn, nullptr, 0, nullptr,
+                          h->st));
+    return HELM_OK;
+}
+
 // x ~= A_2h^{-1} b: right-preconditioned restarted GMRES, preconditioner = a
 // V-cycle starting on level 1, x0 = 0.  FIXED mode runs exactly coarse_iters
 // iterations; TOL mode stops at |g_{j+1}| <= coarse_tol ||b|| (checked on the
@@ -497,7 +574,8 @@ int inner_step_enqueue(helm_ctx *h, int j, int slot)
 // The host needs each step's Hessenberg column only to test convergence, so
 // step j+1 is enqueued before the host waits for step j: the GPU never idles
 // on the read-back.  A converged cycle leaves one speculative step, whose
-// results are not used.
+// results are not used.  With the mixed-precision option the basis is stored
+// in complex64 (everything else, and all arithmetic, stays FP64).
 int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
 {
     const size_t nc = h->L[1].n();
@@ -505,6 +583,7 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
     const bool fixed = h->o.coarse_mode == HELM_CMODE_FIXED;
     const int cap = h->o.coarse_iters;
     const double tol = h->o.coarse_tol;
+    const bool b32 = h->basis32;
     int it = 0;
     if (iters) *iters = 0;
     double bnorm;
@@ -519,11 +598,16 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
     for (;;) {
         double beta;
         if (first) {
-            HCHK(hipMemcpyAsync(h->Vc, b, nc * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
+            if (b32)
+                RCHK(basis32_set0(h, b));
+            else
+                HCHK(hipMemcpyAsync(h->Vc, b, nc * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
             beta = bnorm;  // sig[0] = 1/||b|| was stored by vnorm
         } else {
-            RCHK(coarse_apply(h, x, b, h->Vc));
-            RCHK(vnorm(h, h->Vc, nc, &beta, h->sig));
+            cd *r0 = b32 ? h->wtmp : h->Vc;
+            RCHK(coarse_apply(h, x, b, r0));
+            RCHK(vnorm(h, r0, nc, &beta, h->sig));
+            if (b32) RCHK(basis32_set0(h, r0));
         }
         if (!fixed && beta <= tol * bnorm) break;
         if (it >= cap || beta == 0.0) break;
@@ -532,9 +616,12 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
         const int steps = std::min(m, cap - it);
         int jend = 0;
         bool stop = false;
-        RCHK(inner_step_enqueue(h, 0, 0));
+        auto step = [&](int j, int slot) {
+            return b32 ? inner_step_enqueue32(h, j, slot) : inner_step_enqueue(h, j, slot);
+        };
+        RCHK(step(0, 0));
         for (int j = 0; j < steps; j++) {
-            if (j + 1 < steps) RCHK(inner_step_enqueue(h, j + 1, (j + 1) & 1));
+            if (j + 1 < steps) RCHK(step(j + 1, (j + 1) & 1));
             double hn;
             RCHK(arnoldi_finish(h, j + 1, j & 1, col.data(), &hn));
             const double res = gv.add_column(j, col.data(), hn);
@@ -549,7 +636,10 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
         gv.solve(jend, y);
         for (int i = 0; i < jend; i++) y[i] /= unorm[i];  // v_i = u_i / ||u_i||
         RCHK(upload_y(h, y));
-        HCHK(launch_lincomb(h->Vc, nc, jend, h->ydev, h->wc, nc, 0, h->st));
+        if (b32)
+            HCHK(launch_lincomb32(h->Vc32, nc, jend, h->ydev, h->wc, nc, 0, h->st));
+        else
+            HCHK(launch_lincomb(h->Vc, nc, jend, h->ydev, h->wc, nc, 0, h->st));
         RCHK(vcycle(h, 1, h->wc, x, 1, nullptr));
         if (it >= cap) break;
         if (stop && fixed) break;
@@ -705,7 +795,7 @@ int solve_gcr(helm_ctx *h, const cd *b, cd *x, helm_solve_info *info)
 {
     const auto t0 = std::chrono::steady_clock::now();
     const size_t n = h->L[0].n();
-    const int m = h->m, nb = krylov_blocks(n);
+    const int m = h->m, nb = krylov_blocks(n), nbu = krylov_blocks(n, 1, KB_UPDATE);
     const Lev L0 = h->lev(0);
     const int force = h->o.force_iters;
     const int cap = force > 0 ? force : h->o.maxit;
@@ -761,7 +851,7 @@ int solve_gcr(helm_ctx *h, const cd *b, cd *x, helm_solve_info *info)
                 HCHK(launch_lincomb(Zj, n, 1, h->ydev, x, n, 1, h->st));
                 HCHK(launch_mupdate(r, Wj, n, 1, h->ydev, n, h->partn, nullptr, 0, nullptr,
                                     h->st));
-                HCHK(launch_reduce(h->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, nullptr,
+                HCHK(launch_reduce(h->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, nullptr,
                                    h->st));
                 RCHK(read_norm(h, &rn));
                 if (std::getenv("HELMDEFL_LOG"))
@@ -927,8 +1017,8 @@ int ensure_batch(helm_ctx *h, int B, bool outer)
         if (!rc) rc = dalloc(&W->Vc, (size_t)(h->mc + 1) * b * nc);
         if (!rc) rc = dalloc(&W->wc, b * nc);
         if (!rc) rc = dalloc(&W->zc, b * nc);
-        if (!rc) rc = dalloc(&W->part, b * krylov_blocks(nf) * PSTRIDE);
-        if (!rc) rc = dalloc(&W->partn, b * krylov_blocks(nf) * PSTRIDE);
+        if (!rc) rc = dalloc(&W->part, b * krylov_blocks_max(nf) * PSTRIDE);
+        if (!rc) rc = dalloc(&W->partn, b * krylov_blocks_max(nf) * PSTRIDE);
         if (!rc) rc = dalloc(&W->hbuf, b * SB);
         if (!rc) rc = dalloc(&W->sig, b * SB);
         if (!rc) rc = dalloc(&W->ydev, b * SB);
@@ -1086,7 +1176,7 @@ int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm, int nact)
     BatchWS *W = h->bw;
     const Batch bt{W->B, dm};
     const size_t n = h->L[1].n(), ld = (size_t)W->B * n;
-    const int nb = krylov_blocks(n, W->B);
+    const int nb = krylov_blocks(n, W->B), nbu = krylov_blocks(n, W->B, KB_UPDATE);
     cd *w = W->Vc + (size_t)j1 * ld;
     cd *h1 = W->hbuf, *h2 = W->hbuf + PSTRIDE, *nr = W->hbuf + 2 * PSTRIDE;
     {
@@ -1102,7 +1192,7 @@ int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm, int nact)
     HCHK(launch_mdot(W->Vc, ld, j1, w, n, W->part, 0, h1, j1, h->st, bt, n, n));
     HCHK(launch_reduce(W->part, nb, j1, h2, 0, h1, j1, W->sig, j1, nullptr, h->st, bt));
     HCHK(launch_mupdate(w, W->Vc, ld, j1, h2, n, W->partn, h1, j1, W->sig, h->st, bt, n, n));
-    HCHK(launch_reduce(W->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, W->sig + j1, h->st, bt));
+    HCHK(launch_reduce(W->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, W->sig + j1, h->st, bt));
     HCHK(hipMemcpy2DAsync(W->hpin + (size_t)slot * HB * W->B, HB * sizeof(cd), W->hbuf,
                           SB * sizeof(cd), HB * sizeof(cd), W->B, hipMemcpyDeviceToHost, h->st));
     HCHK(hipEventRecord(W->ev[slot], h->st));
@@ -1292,7 +1382,7 @@ int arnoldi_b(helm_ctx *h, int j1, const int *dm)
     BatchWS *W = h->bw;
     const Batch bt{W->B, dm};
     const size_t n = h->L[0].n(), ld = (size_t)W->B * n;
-    const int nb = krylov_blocks(n, W->B);
+    const int nb = krylov_blocks(n, W->B), nbu = krylov_blocks(n, W->B, KB_UPDATE);
     cd *h1 = W->hbuf, *h2 = W->hbuf + PSTRIDE, *nr = W->hbuf + 2 * PSTRIDE;
     HCHK(launch_mdot(W->V, ld, j1, W->w, n, W->part, 1, nullptr, 0, h->st, bt, n, n));
     HCHK(launch_reduce(W->part, nb, j1 + 1, h1, 0, nullptr, 0, nullptr, 0, nullptr, h->st, bt));
@@ -1301,7 +1391,7 @@ int arnoldi_b(helm_ctx *h, int j1, const int *dm)
     HCHK(launch_mdot(W->V, ld, j1, W->w, n, W->part, 0, h1, j1, h->st, bt, n, n));
     HCHK(launch_reduce(W->part, nb, j1, h2, 0, h1, j1, nullptr, 0, nullptr, h->st, bt));
     HCHK(launch_mupdate(W->w, W->V, ld, j1, h2, n, W->partn, h1, j1, nullptr, h->st, bt, n, n));
-    HCHK(launch_reduce(W->partn, nb, 1, nr, 2, nullptr, 0, nullptr, 0, nullptr, h->st, bt));
+    HCHK(launch_reduce(W->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, nullptr, h->st, bt));
     HCHK(launch_scale(W->w, nr, W->V + (size_t)j1 * ld, n, h->st, bt, n, n));
     HCHK(hipMemcpy2DAsync(W->hpin, HB * sizeof(cd), W->hbuf, SB * sizeof(cd), HB * sizeof(cd),
                           W->B, hipMemcpyDeviceToHost, h->st));
@@ -1529,6 +1619,8 @@ void release(helm_ctx *h)
     dfree(h->wc);
     dfree(h->zc_);
     dfree(h->xin);
+    dfree(h->Vc32);
+    dfree(h->wtmp);
     dfree(h->part);
     dfree(h->partn);
     dfree(h->hbuf);
@@ -1659,7 +1751,12 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (!rc) rc = dalloc(&h->wc, nc);
     if (!rc) rc = dalloc(&h->zc_, nc);
     if (!rc) rc = dalloc(&h->xin, nc);
-    h->part_blocks = krylov_blocks(nf);
+    // with the mixed-precision option the inner basis is complex64 (when the
+    // inner V-cycle has a level below level 1)
+    h->basis32 = o.precision == HELM_PREC_MIXED && h->nlev > 2;
+    if (!rc && h->basis32) rc = dalloc(&h->Vc32, (size_t)(h->mc + 1) * nc);
+    if (!rc && h->basis32) rc = dalloc(&h->wtmp, nc);
+    h->part_blocks = krylov_blocks_max(nf);
     if (!rc) rc = dalloc(&h->part, (size_t)h->part_blocks * PSTRIDE);
     if (!rc) rc = dalloc(&h->partn, (size_t)h->part_blocks * PSTRIDE);
     if (!rc) rc = dalloc(&h->hbuf, (size_t)HBUF);

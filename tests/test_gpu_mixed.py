@@ -60,8 +60,32 @@ def test_mixed_deflate_apply_parity(H, ora, case):
     got = host(S.deflate(dev(v), 2))
     want, _ = ora.deflate_apply(Po, v, 2)
     assert rel(got, want) <= 1e-5
-    # the Q and P parts do not involve the fine-grid cycle: still FP64-exact
-    assert rel(host(S.deflate(dev(v), 1)), ora.deflate_apply(Po, v, 1)[0]) <= 1e-11
+    # the Q and P parts do not involve the fine-grid cycle, but their coarse
+    # solve stores its Krylov basis in complex64 (when the inner V-cycle has a
+    # level below level 1): FP32 level
+    assert rel(host(S.deflate(dev(v), 1)), ora.deflate_apply(Po, v, 1)[0]) <= 1e-5
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c[1] * c[2] >= 97 * 161],
+                         ids=[c[0] for c in CASES if c[1] * c[2] >= 97 * 161])
+def test_mixed_coarse_solve_basis32(H, ora, case):
+    """The coarse GMRES with the complex64 basis (FP64 operators and sums)
+    against the FP64 oracle at a fixed iteration count, over two restarts: FP32
+    level, and measurably not the FP64 result."""
+    n_it = 12
+    S, P = make_pair(H, ora, case, coarse_mode=1, coarse_iters=n_it, coarse_restart=5,
+                     precision=MIXED)
+    S64, _ = make_pair(H, ora, case, coarse_mode=1, coarse_iters=n_it, coarse_restart=5)
+    Po = P.replace(coarse_mode=ora.CMODE_FIXED, coarse_iters=n_it, coarse_restart=5)
+    nxc, nyc = S.coarse_dims()
+    v1 = inputs.random_complex((nyc, nxc), 107)
+    got, it = S.coarse_solve(dev(v1))
+    got64, it64 = S64.coarse_solve(dev(v1))
+    want, ito = ora.coarse_solve(Po, v1)
+    assert it == it64 == ito
+    assert rel(host(got64), want) <= 1e-11
+    d = rel(host(got), want)
+    assert 1e-12 < d <= 1e-5, d
 
 
 def _wedge_pair(H, ora, w, **kw):
