@@ -164,6 +164,10 @@ hipError_t launch_zt(const Lev &Lf, const Lev &Lc, int zho, const cd *vf, const 
 // vf = Z vc.
 hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf, hipStream_t st,
                     Batch bt = Batch{});
+// y = Z^T A_h Z x, or y = b - Z^T A_h Z x (the Galerkin coarse operator, one
+// launch; the fine-grid intermediates stay in LDS).
+hipError_t launch_glk(const Lev &Lf, const Lev &Lc, int zho, const cd *x, const cd *b, cd *y,
+                      hipStream_t st, Batch bt = Batch{});
 // t = v - A_h (Z v2).
 hipError_t launch_dresid(const Lev &Lf, const Lev &Lc, int zho, const cd *v, const cd *v2,
                          cd *t, hipStream_t st, Batch bt = Batch{});

@@ -115,7 +115,7 @@ constexpr int NMASK = 64;            // rotating active-mask buffers
 struct BatchWS {
     int B = 0;
     cd *lr[MAXLEV] = {}, *lx[MAXLEV] = {};
-    cd *v1 = nullptr, *v2 = nullptr, *tf = nullptr, *f1 = nullptr, *f2 = nullptr;
+    cd *v1 = nullptr, *v2 = nullptr, *tf = nullptr;
     cd *Vc = nullptr, *wc = nullptr, *zc = nullptr;
     cd *part = nullptr, *partn = nullptr;
     cd *hbuf = nullptr, *sig = nullptr, *ydev = nullptr;
@@ -145,7 +145,7 @@ struct helm_ctx {
     int ncoarsest = 0;
 
     // deflation workspace (coarse grid = level 1)
-    cd *v1 = nullptr, *v2 = nullptr, *tf = nullptr, *f1 = nullptr, *f2 = nullptr;
+    cd *v1 = nullptr, *v2 = nullptr, *tf = nullptr;
     // inner GMRES
     int mc = 0;
     cd *Vc = nullptr, *wc = nullptr, *zc_ = nullptr, *xin = nullptr;
@@ -503,10 +503,10 @@ int coarse_apply(helm_ctx *h, const cd *x, const cd *b, cd *y)
         }
         return HELM_OK;
     }
-    Timed tm(h, HELM_K_COARSE, 1, (b ? 48.0 : 32.0) * nc + 64.0 * nf);
-    HCHK(launch_z(Lf, Lc, h->zho, x, h->f1, h->st));
-    HCHK(launch_apply5(Lf, make_double2(1.0, 0.0), h->f1, nullptr, h->f2, h->st));
-    HCHK(launch_zt(Lf, Lc, h->zho, h->f2, b, y, h->st));
+    // Galerkin: Z^T A_h Z in one launch (coarse vectors in and out, plus the
+    // fine wavenumber on a variable-k grid)
+    Timed tm(h, HELM_K_COARSE, 1, (b ? 48.0 : 32.0) * nc + (Lf.k ? 8.0 * nf : 0.0));
+    HCHK(launch_glk(Lf, Lc, h->zho, x, b, y, h->st));
     return HELM_OK;
 }
 
@@ -978,7 +978,7 @@ void free_batch(BatchWS *W)
         dfree(W->lr[l]);
         dfree(W->lx[l]);
     }
-    for (void *p : {(void *)W->v1, (void *)W->v2, (void *)W->tf, (void *)W->f1, (void *)W->f2,
+    for (void *p : {(void *)W->v1, (void *)W->v2, (void *)W->tf,
                     (void *)W->Vc, (void *)W->wc, (void *)W->zc, (void *)W->part,
                     (void *)W->partn, (void *)W->hbuf, (void *)W->sig, (void *)W->ydev,
                     (void *)W->V, (void *)W->Z, (void *)W->w, (void *)W->bm, (void *)W->dmask})
@@ -1012,8 +1012,6 @@ int ensure_batch(helm_ctx *h, int B, bool outer)
         if (!rc) rc = dalloc(&W->v1, b * nc);
         if (!rc) rc = dalloc(&W->v2, b * nc);
         if (!rc) rc = dalloc(&W->tf, b * nf);
-        if (!rc && h->o.coarse_op == HELM_COARSE_GALERKIN) rc = dalloc(&W->f1, b * nf);
-        if (!rc && h->o.coarse_op == HELM_COARSE_GALERKIN) rc = dalloc(&W->f2, b * nf);
         if (!rc) rc = dalloc(&W->Vc, (size_t)(h->mc + 1) * b * nc);
         if (!rc) rc = dalloc(&W->wc, b * nc);
         if (!rc) rc = dalloc(&W->zc, b * nc);
@@ -1160,10 +1158,7 @@ int coarse_apply_b(helm_ctx *h, const cd *x, const cd *b, cd *y, const int *dm)
     case HELM_COARSE_REDGLK1: HCHK(launch_redglk2(Lc, x, b, y, 1, h->st, bt)); break;
     case HELM_COARSE_REDO4: HCHK(launch_redo4(Lc, x, b, y, h->st, bt)); break;
     case HELM_COARSE_REDO2: HCHK(launch_apply5(Lc, make_double2(1.0, 0.0), x, b, y, h->st, bt)); break;
-    default:
-        HCHK(launch_z(Lf, Lc, h->zho, x, W->f1, h->st, bt));
-        HCHK(launch_apply5(Lf, make_double2(1.0, 0.0), W->f1, nullptr, W->f2, h->st, bt));
-        HCHK(launch_zt(Lf, Lc, h->zho, W->f2, b, y, h->st, bt));
+    default: HCHK(launch_glk(Lf, Lc, h->zho, x, b, y, h->st, bt));
     }
     return HELM_OK;
 }
@@ -1613,8 +1608,6 @@ void release(helm_ctx *h)
     dfree(h->v1);
     dfree(h->v2);
     dfree(h->tf);
-    dfree(h->f1);
-    dfree(h->f2);
     dfree(h->Vc);
     dfree(h->wc);
     dfree(h->zc_);
@@ -1745,8 +1738,6 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (!rc) rc = dalloc(&h->v1, nc);
     if (!rc) rc = dalloc(&h->v2, nc);
     if (!rc) rc = dalloc(&h->tf, nf);
-    if (!rc && o.coarse_op == HELM_COARSE_GALERKIN) rc = dalloc(&h->f1, nf);
-    if (!rc && o.coarse_op == HELM_COARSE_GALERKIN) rc = dalloc(&h->f2, nf);
     if (!rc) rc = dalloc(&h->Vc, (size_t)(h->mc + 1) * nc);
     if (!rc) rc = dalloc(&h->wc, nc);
     if (!rc) rc = dalloc(&h->zc_, nc);

@@ -855,6 +855,204 @@ hipError_t launch_z(const Lev &Lf, const Lev &Lc, int zho, const cd *vc, cd *vf,
 }
 
 // ------------------------------------------------------------------------
+// Galerkin coarse operator y = Z^T A_h Z x (or y = b - Z^T A_h Z x) in one
+// launch (Section 5.2.1): a block owns a ZT_CX x ZT_CY coarse tile and
+// computes, in LDS, x on the coarse nodes around it, Z x on the fine nodes
+// the tile's Z^T needs plus one more ring, A_h (Z x) on the former, and Z^T
+// of that, so the fine-grid vectors Z x and A_h Z x never reach memory.  Each
+// step is the arithmetic, in its order, of k_z, k_apply5 and k_zt above.
+// ------------------------------------------------------------------------
+constexpr int GK_CW = ZT_CX + 4, GK_CH = ZT_CY + 4;  // coarse x: I0-2 .. I0+CX+1
+constexpr int GK_1W = 2 * ZT_CX + 5, GK_1H = 2 * ZT_CY + 5;  // Z x: fi0-1 .. fi0+2CX+3
+constexpr int GK_2W = ZT_W, GK_2H = ZT_H;  // A_h Z x: fi0 .. fi0+2CX+2 (fi0 = 2 I0 - 2)
+
+// (Z x) at fine node (i,j) from the LDS coarse tile sc (origin I0-2, J0-2):
+// prolong_at with the coarse values read from the tile.
+__device__ __forceinline__ cd prolong_lds(const Lev &Lc, const cd (*sc)[GK_CW], int ci0, int cj0,
+                                          int i, int j, int zho)
+{
+    int Ix[3], Jy[3];
+    double wx[3], wy[3];
+    const int nxw = zrule(i, zho, Ix, wx), nyw = zrule(j, zho, Jy, wy);
+    cd s = czero();
+    for (int b = 0; b < nyw; b++) {
+        const int J = Jy[b];
+        if (J < 0 || J >= Lc.ny) continue;
+        for (int a = 0; a < nxw; a++) {
+            const int I = Ix[a];
+            if (I < 0 || I >= Lc.nx || !unknown(Lc, I, J)) continue;
+            caxpy(s, wx[a] * wy[b], sc[J - cj0][I - ci0]);
+        }
+    }
+    return s;
+}
+
+template <bool RESID, bool VARK>
+__global__ __launch_bounds__(256) void k_glk(Lev Lf, Lev Lc, int zho, const cd *__restrict__ x,
+                                             const cd *__restrict__ b, cd *__restrict__ y,
+                                             int tiles_x, Batch bt)
+{
+    if (skip_rhs(bt)) return;
+    {
+        const size_t nc = (size_t)Lc.nx * Lc.ny;
+        x += blockIdx.y * nc;
+        if (RESID) b += blockIdx.y * nc;
+        y += blockIdx.y * nc;
+    }
+    __shared__ cd sc[GK_CH][GK_CW];
+    __shared__ cd s1[GK_1H * GK_1W];  // Z x, later the horizontal Z^T sums
+    __shared__ cd s2[GK_2H][GK_2W];
+    __shared__ double sk[VARK ? GK_2H : 1][VARK ? GK_2W : 1];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int I0 = (t % tiles_x) * ZT_CX, J0 = (t / tiles_x) * ZT_CY;
+    const int ci0 = I0 - 2, cj0 = J0 - 2, fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
+    // ---- loads: coarse x (0 outside the grid or at non-unknowns; those
+    // nodes are skipped by prolong_lds anyway), k on the A_h nodes
+    constexpr int NC = GK_CW * GK_CH, NK = GK_2W * GK_2H;
+    cd xv[(NC + 255) / 256];
+    double mx[(NC + 255) / 256], kv[VARK ? (NK + 255) / 256 : 1];
+#pragma unroll
+    for (int kq = 0; kq < (NC + 255) / 256; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        const int I = ci0 + q % GK_CW, J = cj0 + q / GK_CW;
+        const bool in = q < NC && I >= 0 && I < Lc.nx && J >= 0 && J < Lc.ny && unknown(Lc, I, J);
+        xv[kq] = x[in ? (size_t)J * Lc.nx + I : 0];
+        mx[kq] = in ? 1.0 : 0.0;
+    }
+    if (VARK) {
+#pragma unroll
+        for (int kq = 0; kq < (NK + 255) / 256; kq++) {
+            const int q = threadIdx.x + 256 * kq;
+            const int i = fi0 + q % GK_2W, j = fj0 + q / GK_2W;
+            const bool in = q < NK && i >= 0 && i < Lf.nx && j >= 0 && j < Lf.ny;
+            kv[kq] = Lf.k[in ? (size_t)j * Lf.nx + i : 0];
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kq = 0; kq < (NC + 255) / 256; kq++) {
+        const int q = threadIdx.x + 256 * kq;
+        if (q < NC) sc[q / GK_CW][q % GK_CW] = cscal(mx[kq], xv[kq]);
+    }
+    if (VARK) {
+#pragma unroll
+        for (int kq = 0; kq < (NK + 255) / 256; kq++) {
+            const int q = threadIdx.x + 256 * kq;
+            if (q < NK) sk[q / GK_2W][q % GK_2W] = kv[kq];
+        }
+    }
+    __syncthreads();
+    // ---- Z x on fine nodes fi0-1 .. fi0+2CX+3 (k_z: 0 at non-unknowns),
+    // separably: along x into s2 (GK_CH coarse rows x GK_1W fine columns;
+    // coarse nodes outside the grid or not unknowns hold 0 in sc), then along
+    // y into s1
+    cd *sh = &s2[0][0];  // GK_CH * GK_1W <= GK_2H * GK_2W entries
+    const double zw0 = zho ? 0.75 : 1.0, zw1 = zho ? 0.125 : 0.0;
+    for (int q = threadIdx.x; q < GK_CH * GK_1W; q += 256) {
+        const int r = q / GK_1W, a1 = q % GK_1W;
+        const int i = fi0 - 1 + a1, ci = (i >> 1) - ci0;  // coarse I = floor(i / 2)
+        cd v;
+        if (i & 1) {
+            v = cscal(0.5, cadd(sc[r][ci], sc[r][ci + 1]));
+        } else {
+            v = cscal(zw0, sc[r][ci]);
+            if (zho) caxpy(v, zw1, cadd(sc[r][ci - 1], sc[r][ci + 1]));
+        }
+        sh[q] = v;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < GK_1W * GK_1H; q += 256) {
+        const int a1 = q % GK_1W, b1 = q / GK_1W;
+        const int i = fi0 - 1 + a1, j = fj0 - 1 + b1, cj = (j >> 1) - cj0;
+        cd v = czero();
+        if (i >= 0 && i < Lf.nx && j >= 0 && j < Lf.ny && unknown(Lf, i, j)) {
+            if (j & 1) {
+                v = cscal(0.5, cadd(sh[cj * GK_1W + a1], sh[(cj + 1) * GK_1W + a1]));
+            } else {
+                v = cscal(zw0, sh[cj * GK_1W + a1]);
+                if (zho) caxpy(v, zw1, cadd(sh[(cj - 1) * GK_1W + a1], sh[(cj + 1) * GK_1W + a1]));
+            }
+        }
+        s1[q] = v;
+    }
+    __syncthreads();
+    // ---- A_h (Z x) on fine nodes fi0 .. fi0+2CX+2 (k_apply5; 0 outside the
+    // grid and at non-unknowns, as k_zt reads it).  Away from the grid edge
+    // the stencil is the interior one (Z x is 0 at Dirichlet boundary nodes,
+    // so their dropped couplings add nothing).
+    const bool som = Lf.bc == BC_SOM;
+    for (int q = threadIdx.x; q < GK_2W * GK_2H; q += 256) {
+        const int a = q % GK_2W, bb = q / GK_2W;
+        const int i = fi0 + a, j = fj0 + bb;
+        const int c = (bb + 1) * GK_1W + a + 1;  // (i,j) in s1
+        cd v = czero();
+        const bool inner = i > 0 && j > 0 && i < Lf.nx - 1 && j < Lf.ny - 1;
+        if (inner) {
+            const double k = VARK ? sk[bb][a] : Lf.kc;
+            const cd ap = make_double2(2.0 * Lf.ihx2 + 2.0 * Lf.ihy2 - k * k, -0.0 * (k * k));
+            v = cmul(ap, s1[c]);
+            caxpy(v, -Lf.ihx2, s1[c - 1]);
+            caxpy(v, -Lf.ihx2, s1[c + 1]);
+            caxpy(v, -Lf.ihy2, s1[c - GK_1W]);
+            caxpy(v, -Lf.ihy2, s1[c + GK_1W]);
+        } else if (som && i >= 0 && i < Lf.nx && j >= 0 && j < Lf.ny) {
+            cd ap;
+            double aw, ae, as, an;
+            coef5k(Lf, make_double2(1.0, 0.0), i, j, VARK ? sk[bb][a] : Lf.kc, ap, aw, ae, as, an);
+            v = cmul(ap, s1[c]);
+            if (aw != 0.0) caxpy(v, aw, s1[c - 1]);
+            if (ae != 0.0) caxpy(v, ae, s1[c + 1]);
+            if (as != 0.0) caxpy(v, as, s1[c - GK_1W]);
+            if (an != 0.0) caxpy(v, an, s1[c + GK_1W]);
+        }
+        s2[bb][a] = v;
+    }
+    __syncthreads();
+    // ---- Z^T (k_zt): rows first, into s1 as sx[GK_2H][ZT_CX]
+    const double w0 = zho ? 0.75 : 1.0, w1 = 0.5, w2 = zho ? 0.125 : 0.0;
+    for (int q = threadIdx.x; q < ZT_CX * GK_2H; q += 256) {
+        const int c = q % ZT_CX, bb = q / ZT_CX;
+        const int a = 2 * c + 2;
+        cd v = cscal(w0, s2[bb][a]);
+        caxpy(v, w1, cadd(s2[bb][a - 1], s2[bb][a + 1]));
+        if (zho) caxpy(v, w2, cadd(s2[bb][a - 2], s2[bb][a + 2]));
+        s1[bb * ZT_CX + c] = v;
+    }
+    __syncthreads();
+    const int c = threadIdx.x % ZT_CX, rl = threadIdx.x / ZT_CX;
+    const int I = I0 + c, J = J0 + rl;
+    if (I >= Lc.nx || J >= Lc.ny) return;
+    cd v = czero();
+    if (unknown(Lc, I, J)) {
+        const int bb = 2 * rl + 2;
+        v = cscal(w0, s1[bb * ZT_CX + c]);
+        caxpy(v, w1, cadd(s1[(bb - 1) * ZT_CX + c], s1[(bb + 1) * ZT_CX + c]));
+        if (zho) caxpy(v, w2, cadd(s1[(bb - 2) * ZT_CX + c], s1[(bb + 2) * ZT_CX + c]));
+        if (RESID) v = csub(b[(size_t)J * Lc.nx + I], v);
+    }
+    y[(size_t)J * Lc.nx + I] = v;
+}
+
+hipError_t launch_glk(const Lev &Lf, const Lev &Lc, int zho, const cd *x, const cd *b, cd *y,
+                      hipStream_t st, Batch bt)
+{
+    const int tx = cdiv(Lc.nx, ZT_CX), ty = cdiv(Lc.ny, ZT_CY);
+    const dim3 g(tx * ty, bt.B);
+    if (Lf.k) {
+        if (b)
+            k_glk<true, true><<<g, 256, 0, st>>>(Lf, Lc, zho, x, b, y, tx, bt);
+        else
+            k_glk<false, true><<<g, 256, 0, st>>>(Lf, Lc, zho, x, b, y, tx, bt);
+    } else {
+        if (b)
+            k_glk<true, false><<<g, 256, 0, st>>>(Lf, Lc, zho, x, b, y, tx, bt);
+        else
+            k_glk<false, false><<<g, 256, 0, st>>>(Lf, Lc, zho, x, b, y, tx, bt);
+    }
+    HD_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------------
 // Deflated residual t = v - A_h (Z v2), with Z v2 staged in LDS (66 x 18) and
 // never written to memory.
 // ------------------------------------------------------------------------
