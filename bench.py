@@ -46,8 +46,11 @@ def parse():
     ap.add_argument("--freq", type=float, default=10.0, help="layered: frequency in Hz")
     ap.add_argument("--batch", type=int, choices=[0, 1], default=1,
                     help="layered: 1 = one batched solve of all sources, 0 = one after another")
+    ap.add_argument("--graphs", type=int, choices=[0, 1], default=0,
+                    help="1 = coarse-GMRES steps replayed from captured HIP graphs")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
-                    help="mixed: complex64 fine-grid V-cycle inside the FP64 solve")
+                    help="mixed: complex64 fine-grid V-cycle and coarse-GMRES basis inside the "
+                         "FP64 solve")
     ap.add_argument("--roofline-kernel", default="mdot",
                     help="kernel class whose roofline is reported")
     ap.add_argument("--roofline-level", type=int, default=1,
@@ -138,7 +141,8 @@ def adjoint_bench(a, torch, H, inputs):
     omega = 2 * 3.141592653589793 * c["freq"]
     grid = (c["nx"], c["ny"], c["h"], c["h"], H.BC_SOMMERFELD)
     opts = dict(coarse_op=H.COARSE_REDGLK2, coarse_mode=H.CMODE_TOL, coarse_tol=0.1,
-                coarse_iters=300, coarse_restart=15, restart=20, tol=1e-6, batch=a.batch)
+                coarse_iters=300, coarse_restart=15, restart=20, tol=1e-6, batch=a.batch,
+                graphs=a.graphs)
     src = torch.from_numpy(c["sources"]).cuda()
     rec = torch.from_numpy(c["rec"]).cuda()
     kt = (omega * torch.sqrt(torch.from_numpy(c["s_true"]))).cuda()
@@ -211,7 +215,7 @@ def main():
                  k=None if kf is None else torch.from_numpy(kf).cuda(), kconst=w.kconst,
                  coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
                  coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart, restart=w.restart,
-                 tol=w.tol, precision=prec, batch=a.batch)
+                 tol=w.tol, precision=prec, batch=a.batch, graphs=a.graphs)
     nrhs = w.nsrc if w.model == "layered" else 1
     b = torch.from_numpy(w.sources() if nrhs > 1 else w.rhs()).cuda()
     x = torch.zeros_like(b)
@@ -258,11 +262,12 @@ def main():
             "source": "gaussian sigma=2h" if w.source == "gauss" else "point",
             "preconditioner": "APD (Bezier Z, " + ("ReD-Glk2" if w.coarse_op else "Galerkin")
                               + " A_2h) + 1 CSLP V-cycle (1,0.5)"
-                              + (" in complex64" if prec == H.PREC_MIXED else ""),
+                              + (" in complex64, complex64 coarse basis" if prec == H.PREC_MIXED
+                                 else ""),
             "krylov": f"FGMRES({w.restart}) to {w.tol:g}",
             "coarse_solve": f"GMRES({w.coarse_restart}) to {w.coarse_tol:g}",
             "outer_iters": last["outer_iters"], "inner_iters_total": last["inner_iters_total"],
-            "relres": last["relres"],
+            "relres": last["relres"], "graphs": bool(a.graphs),
             **({"nrhs": nrhs, "batched": bool(a.batch),
                 "outer_iters_max": max(i["outer_iters"] for i in infos[-1]),
                 "inner_iters_sum": sum(i["inner_iters_total"] for i in infos[-1]),

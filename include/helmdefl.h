@@ -120,6 +120,15 @@ typedef struct {
                                 converged ones out); 0 = one after another.
                                 GCR, left GMRES and the mixed-precision option
                                 always go one after another. */
+    int graphs;              /* 0 (default): every kernel is launched directly.
+                                1: each step of the coarse GMRES (V-cycle, A_2h,
+                                Gram-Schmidt kernels) is captured once per basis
+                                index into a HIP graph and replayed, one launch per
+                                step instead of about twenty (not while kernel
+                                timing is enabled; the batched path launches
+                                directly).  Results are identical either way; on
+                                MI355X the replay measured no faster, the cost of
+                                each dependent kernel being on the device side. */
 } helm_opts;
 
 /* Per right-hand side result of helm_solve. */

@@ -169,6 +169,11 @@ struct helm_ctx {
     cd *adjb = nullptr;              // adjoint solve right-hand sides
     size_t adjb_n = 0;
 
+    // captured coarse-GMRES steps, one per basis index (null until first use);
+    // graph_off after a capture failed
+    std::vector<hipGraphExec_t> gstep;
+    bool graph_off = false;
+
     // kernel timing
     int t_cls = -1, t_lev = -1;
     std::vector<hipEvent_t> ev_free;
@@ -321,13 +326,24 @@ int arnoldi_step(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col
     return HELM_OK;
 }
 
+// Copy an inner step's scalars (projections, second-pass projections, norm)
+// to pinned slot `slot` and record the slot's event.
+int step_readback(helm_ctx *h, int slot)
+{
+    HCHK(hipMemcpyAsync(h->hpin + slot * HBUF, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd),
+                        hipMemcpyDeviceToHost, h->st));
+    HCHK(hipEventRecord(h->ev_slot[slot], h->st));
+    return HELM_OK;
+}
+
 // Arnoldi step of the inner solve on a lazily normalised basis: V[i] holds
 // u_i with v_i = sig[i] u_i.  The new vector w = A z already sits in V[j1];
 // it is orthogonalised in place (same conditional second pass as above) and
 // sig[j1] = 1/||w'|| is stored, so no scaling pass is needed.  Everything is
 // enqueued; the scalars are copied to pinned slot `slot` and ev_slot[slot]
 // is recorded.  arnoldi_finish() waits for that event.
-int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int lev, int slot)
+int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int lev, int slot,
+                         bool readback = true)
 {
     const int nb = krylov_blocks(n), nbu = krylov_blocks(n, 1, KB_UPDATE);
     cd *w = V + (size_t)j1 * ld;
@@ -345,9 +361,7 @@ int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int le
     HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
     HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
     HCHK(launch_reduce(h->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, h->sig + j1, h->st));
-    HCHK(hipMemcpyAsync(h->hpin + slot * HBUF, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd),
-                        hipMemcpyDeviceToHost, h->st));
-    HCHK(hipEventRecord(h->ev_slot[slot], h->st));
+    if (readback) RCHK(step_readback(h, slot));
     return HELM_OK;
 }
 
@@ -511,20 +525,21 @@ int coarse_apply(helm_ctx *h, const cd *x, const cd *b, cd *y)
 }
 
 // One inner Arnoldi step j, enqueued: z = V(v_j), w = A_2h z written into
-// basis slot j+1, then the lazily normalised orthogonalisation.
-int inner_step_enqueue(helm_ctx *h, int j, int slot)
+// basis slot j+1, then the lazily normalised orthogonalisation (and, with
+// readback, the copy of its scalars to pinned slot `slot`).
+int inner_step_enqueue(helm_ctx *h, int j, int slot, bool readback = true)
 {
     const size_t nc = h->L[1].n();
     RCHK(vcycle(h, 1, h->Vc + (size_t)j * nc, h->zc_, 0, nullptr, h->sig + j));
     RCHK(coarse_apply(h, h->zc_, nullptr, h->Vc + (size_t)(j + 1) * nc));
-    return arnoldi_lazy_enqueue(h, h->Vc, nc, j + 1, nc, 1, slot);
+    return arnoldi_lazy_enqueue(h, h->Vc, nc, j + 1, nc, 1, slot, readback);
 }
 
 // The same step on the complex64 basis (mixed precision): A_2h z is formed
 // in FP64 in wtmp; the first Gram-Schmidt pass reads it and writes the
 // orthogonalised vector, rounded, into basis slot j1; a second pass (when
 // needed) works in place on that slot.  Products and norms are FP64.
-int arnoldi_lazy_enqueue32(helm_ctx *h, size_t n, int j1, int slot)
+int arnoldi_lazy_enqueue32(helm_ctx *h, size_t n, int j1, int slot, bool readback = true)
 {
     const int nb = krylov_blocks(n, 1, KB_DOT32), nbu = krylov_blocks(n, 1, KB_UPDATE32);
     const size_t ld = n;
@@ -544,18 +559,54 @@ int arnoldi_lazy_enqueue32(helm_ctx *h, size_t n, int j1, int slot)
     HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
     HCHK(launch_mupdate32(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
     HCHK(launch_reduce(h->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, h->sig + j1, h->st));
-    HCHK(hipMemcpyAsync(h->hpin + slot * HBUF, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd),
-                        hipMemcpyDeviceToHost, h->st));
-    HCHK(hipEventRecord(h->ev_slot[slot], h->st));
+    if (readback) RCHK(step_readback(h, slot));
     return HELM_OK;
 }
 
-int inner_step_enqueue32(helm_ctx *h, int j, int slot)
+int inner_step_enqueue32(helm_ctx *h, int j, int slot, bool readback = true)
 {
     const size_t nc = h->L[1].n();
     RCHK(vcycle32(h, h->Vc32 + (size_t)j * nc, h->zc_, h->sig + j));
     RCHK(coarse_apply(h, h->zc_, nullptr, h->wtmp));
-    return arnoldi_lazy_enqueue32(h, nc, j + 1, slot);
+    return arnoldi_lazy_enqueue32(h, nc, j + 1, slot, readback);
+}
+
+// Inner step j through a HIP graph: its kernels (they depend on j only: the
+// basis slots, the Gram-Schmidt length) are captured on first use and
+// replayed from then on, one launch instead of about twenty.  The scalar
+// read-back and its event stay ordinary stream work, so the graph holds
+// kernel nodes only.  Off while kernel timing is on; a failed capture turns
+// graphs off for this context and the step is launched directly.
+int inner_step_run(helm_ctx *h, int j, int slot)
+{
+    const bool b32 = h->basis32;
+    auto direct = [&](bool rb) {
+        return b32 ? inner_step_enqueue32(h, j, slot, rb) : inner_step_enqueue(h, j, slot, rb);
+    };
+    if (!h->o.graphs || h->graph_off || h->t_cls >= 0) return direct(true);
+    if ((int)h->gstep.size() <= j) h->gstep.resize(j + 1, nullptr);
+    if (!h->gstep[j]) {
+        if (hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            h->graph_off = true;
+            return direct(true);
+        }
+        const int rc = direct(false);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(h->st, &g);
+        hipGraphExec_t ex = nullptr;
+        if (rc == HELM_OK && ec == hipSuccess && g &&
+            hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+            h->gstep[j] = ex;
+        } else {
+            (void)hipGetLastError();
+            h->graph_off = true;
+        }
+        if (g) (void)hipGraphDestroy(g);
+        if (h->graph_off) return direct(true);
+    }
+    HCHK(hipGraphLaunch(h->gstep[j], h->st));
+    return step_readback(h, slot);
 }
 
 // Basis slot 0 (complex64) = u (FP64), rounded.
@@ -616,9 +667,7 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
         const int steps = std::min(m, cap - it);
         int jend = 0;
         bool stop = false;
-        auto step = [&](int j, int slot) {
-            return b32 ? inner_step_enqueue32(h, j, slot) : inner_step_enqueue(h, j, slot);
-        };
+        auto step = [&](int j, int slot) { return inner_step_run(h, j, slot); };
         RCHK(step(0, 0));
         for (int j = 0; j < steps; j++) {
             if (j + 1 < steps) RCHK(step(j + 1, (j + 1) & 1));
@@ -1594,6 +1643,9 @@ int setup_coarsest(helm_ctx *h, const std::vector<std::vector<double>> &khost)
 
 void release(helm_ctx *h)
 {
+    for (hipGraphExec_t &e : h->gstep)
+        if (e) (void)hipGraphExecDestroy(e);
+    h->gstep.clear();
     if (!h) return;
     if (h->st) (void)hipStreamSynchronize(h->st);
     for (int l = 0; l < h->nlev; l++) {
@@ -1660,6 +1712,7 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
         return HELM_EINVAL;
     if (o.outer < HELM_OUTER_FGMRES || o.outer > HELM_OUTER_GMRES_LEFT) return HELM_EINVAL;
     if (o.batch != 0 && o.batch != 1) return HELM_EINVAL;
+    if (o.graphs != 0 && o.graphs != 1) return HELM_EINVAL;
     if (o.coarse_mode != HELM_CMODE_FIXED && o.coarse_mode != HELM_CMODE_TOL) return HELM_EINVAL;
     if (o.coarse_iters < 1 || o.coarse_restart < 1 || o.coarse_restart > MAX_RESTART)
         return HELM_EINVAL;
@@ -1810,6 +1863,7 @@ int helm_opts_default(helm_opts *o)
     o->precision = HELM_PREC_FP64;
     o->outer = HELM_OUTER_FGMRES;
     o->batch = 1;
+    o->graphs = 0;
     return HELM_OK;
 }
 

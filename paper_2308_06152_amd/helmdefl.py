@@ -51,7 +51,8 @@ class Opts(ctypes.Structure):
                 ("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("tol", ctypes.c_double),
                 ("x0_given", ctypes.c_int), ("force_iters", ctypes.c_int),
                 ("coarsest_nodes", ctypes.c_int), ("precision", ctypes.c_int),
-                ("outer", ctypes.c_int), ("batch", ctypes.c_int)]
+                ("outer", ctypes.c_int), ("batch", ctypes.c_int),
+                ("graphs", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -50,6 +50,7 @@ def test_defaults_and_strerror(H):
     assert o.precision == H.PREC_FP64
     assert o.outer == H.OUTER_FGMRES
     assert o.batch == 1
+    assert o.graphs == 0
     L = H.load()
     assert L.helm_strerror(0) == b"success"
     assert b"coarsen" in L.helm_strerror(H.HELM_EGRID)
@@ -76,7 +77,8 @@ def test_create_rejects_uncoarsenable_grids(H, nx, ny):
                                 dict(omega=0.0), dict(tol=-1.0), dict(coarsest_nodes=-1),
                                 dict(coarsest_nodes=5000), dict(precision=2),
                                 dict(precision=-1), dict(coarse_op=5), dict(coarse_op=-1),
-                                dict(outer=3), dict(outer=-1), dict(batch=2)])
+                                dict(outer=3), dict(outer=-1), dict(batch=2),
+                                dict(graphs=2), dict(graphs=-1)])
 def test_create_rejects_bad_options(H, kw):
     assert _create(H, 9, 9, **kw) == H.HELM_EINVAL
 
