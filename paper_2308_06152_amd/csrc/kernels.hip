@@ -161,6 +161,29 @@ __device__ __forceinline__ cd prolong_at(const Lev &Lc, const cd *__restrict__ v
     return s;
 }
 
+// The same sum with the coarse values read from an LDS tile whose entry
+// [J - cj0][I - ci0] holds vc at coarse node (I, J) (the tile must cover
+// every coarse node the rule reaches from (i, j)).
+template <int W>
+__device__ __forceinline__ cd prolong_tile(const Lev &Lc, const cd (*t)[W], int ci0, int cj0,
+                                           int i, int j, int zho)
+{
+    int Ix[3], Jy[3];
+    double wx[3], wy[3];
+    const int nxw = zrule(i, zho, Ix, wx), nyw = zrule(j, zho, Jy, wy);
+    cd s = czero();
+    for (int b = 0; b < nyw; b++) {
+        const int J = Jy[b];
+        if (J < 0 || J >= Lc.ny) continue;
+        for (int a = 0; a < nxw; a++) {
+            const int I = Ix[a];
+            if (I < 0 || I >= Lc.nx || !unknown(Lc, I, J)) continue;
+            caxpy(s, wx[a] * wy[b], t[J - cj0][I - ci0]);
+        }
+    }
+    return s;
+}
+
 // ------------------------------------------------------------------------
 // 5-point operator: y = op x  or  y = b - op x
 // Block: 64 x 4 threads; each thread owns one column of a 64 x 16 tile and
@@ -490,7 +513,7 @@ constexpr int VU_TX = 64, VU_TY = 16;
 constexpr int VU_W = VU_TX + 2, VU_H = VU_TY + 2;
 constexpr int VU_CW = VU_TX / 2 + 2, VU_CH = VU_TY / 2 + 2;  // 34 x 10
 
-template <bool VARK, class RI, class R, class RO>
+template <bool VARK, class RI, class R, class RO, bool V2>
 __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omega, Smooth<R> c,
                                                const cx<RI> *__restrict__ r,
                                                const cd *__restrict__ rs,
@@ -515,6 +538,8 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
     const R rsc = rs ? (R)rs[0].x : (R)1;  // right-hand side = rsc * r
     __shared__ C sx2[VU_H][VU_W];
     __shared__ C se[VU_CH][VU_CW];
+    // Z v2 term (level 0 only, V2): v2 on the coarse tile
+    __shared__ cd sv2[V2 ? VU_CH : 1][V2 ? VU_CW : 1];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int i0 = (t % tiles_x) * VU_TX, j0 = (t / tiles_x) * VU_TY;
     const int ci0 = i0 / 2 - 1, cj0 = j0 / 2 - 1;  // coarse tile origin
@@ -573,6 +598,19 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
             oold[rr] = out[i < Lf.nx && j < Lf.ny ? (size_t)j * Lf.nx + i : 0];
         }
     }
+    // v2 on the same coarse tile as ec: every coarse node the Z rule reaches
+    // from the owned fine nodes (prolong_at skips those outside the grid or
+    // not unknowns, so their entries are never read)
+    cd v2l[V2 ? NKC : 1];
+    if constexpr (V2) {
+#pragma unroll
+        for (int kq = 0; kq < NKC; kq++) {
+            const int q = threadIdx.x + 256 * kq;
+            const int I = ci0 + q % VU_CW, J = cj0 + q / VU_CW;
+            const bool in = q < NC && I >= 0 && I < Lc.nx && J >= 0 && J < Lc.ny;
+            v2l[kq] = v2[in ? (size_t)J * Lc.nx + I : 0];
+        }
+    }
     {
         const int fi = i0 - 1 + ha, fj = j0 - 1 + hb;
         const bool in = ha >= 0 && fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny &&
@@ -594,6 +632,8 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
     for (int kq = 0; kq < NKC; kq++) {
         const int q = threadIdx.x + 256 * kq;
         if (q < NC) se[q / VU_CW][q % VU_CW] = el[kq];
+        if constexpr (V2)
+            if (q < NC) sv2[q / VU_CW][q % VU_CW] = v2l[kq];
     }
     __syncthreads();
     // ---- x2 = omega D^-1 r + P ec at the owned nodes and the halo node
@@ -641,7 +681,7 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
             caxpy(m, as, sx2[bb - 1][a]);
             caxpy(m, an, sx2[bb + 1][a]);
             v = cvt<RO>(cadd(sx2[bb][a], cmul(wv, csub(rown[rr], m))));
-            if (v2) v = cadd(v, cvt<RO>(prolong_at(Lc, v2, i, j, zho)));
+            if constexpr (V2) v = cadd(v, cvt<RO>(prolong_tile(Lc, sv2, ci0, cj0, i, j, zho)));
         }
         if (accumulate) v = cadd(v, oold[rr]);
         out[p] = v;
@@ -656,12 +696,21 @@ static hipError_t vc_up_t(const Lev &Lf, const Lev &Lc, cd s, double omega, cons
     const int tx = cdiv(Lf.nx, VU_TX), ty = cdiv(Lf.ny, VU_TY);
     const Smooth<R> c = smooth_consts<R>(Lf, s, omega);
     const dim3 g(tx * ty, bt.B);
-    if (Lf.k)
-        k_vc_up<true, RI, R, RO><<<g, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out,
-                                                    accumulate, v2, zho, tx, bt);
-    else
-        k_vc_up<false, RI, R, RO><<<g, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out,
-                                                     accumulate, v2, zho, tx, bt);
+#define VU_LAUNCH(VK, V2)                                                                      \
+    k_vc_up<VK, RI, R, RO, V2><<<g, 256, 0, st>>>(Lf, Lc, s, omega, c, r, rs, ec, out, accumulate, \
+                                                  v2, zho, tx, bt)
+    if (Lf.k) {
+        if (v2)
+            VU_LAUNCH(true, true);
+        else
+            VU_LAUNCH(true, false);
+    } else {
+        if (v2)
+            VU_LAUNCH(false, true);
+        else
+            VU_LAUNCH(false, false);
+    }
+#undef VU_LAUNCH
     HD_LAUNCH_CHECK();
 }
 
