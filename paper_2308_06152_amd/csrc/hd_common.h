@@ -229,6 +229,12 @@ hipError_t launch_mupdate32(cf *w, const cf *V, size_t ld, int m, const cd *c, s
 hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, const cd *cond,
                          int jcond, const cd *sig, int nsig, cd *sig_out, hipStream_t st,
                          Batch bt = Batch{});
+// The mode-2 reduction of one vector's norm partials (out[0], sig_out[0] as
+// above), then pub_dst[0, pub_n) = pub_src[0, pub_n) with a system-scope fence:
+// pub_dst is host memory the device can write (the scalars of a Krylov step
+// reach the host without a copy launch).
+hipError_t launch_norm_publish(const cd *part, int nblk, cd *out, cd *sig_out,
+                               const cd *pub_src, int pub_n, cd *pub_dst, hipStream_t st);
 // v = w / nrm[0].x (v = 0 if the norm is 0).
 hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t st,
                         Batch bt = Batch{}, size_t wbs = 0, size_t vbs = 0);

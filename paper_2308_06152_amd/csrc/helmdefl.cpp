@@ -160,6 +160,9 @@ struct helm_ctx {
     cd *hbuf = nullptr, *ydev = nullptr;
     cd *sig = nullptr;   // 1/||u_i|| of the lazily normalised inner basis
     cd *hpin = nullptr;  // pinned: two Arnoldi read-back slots, y staging, norm
+    // pinned, coherent and device-mapped: the inner steps' scalars, two slots
+    // (written by the device; hpub_dev is the device's address of hpub)
+    cd *hpub = nullptr, *hpub_dev = nullptr;
     hipEvent_t ev_slot[2] = {nullptr, nullptr};
     // outer FGMRES (allocated on first solve)
     int m = 0;
@@ -326,12 +329,11 @@ int arnoldi_step(helm_ctx *h, cd *V, size_t ld, int j1, cd *w, size_t n, zc *col
     return HELM_OK;
 }
 
-// Copy an inner step's scalars (projections, second-pass projections, norm)
-// to pinned slot `slot` and record the slot's event.
+// Record slot `slot`'s event after an inner step: the step's last kernel has
+// written its scalars (projections, second-pass projections, norm) to the
+// host-visible slot hpub + slot * HBUF.
 int step_readback(helm_ctx *h, int slot)
 {
-    HCHK(hipMemcpyAsync(h->hpin + slot * HBUF, h->hbuf, (2 * PSTRIDE + 1) * sizeof(cd),
-                        hipMemcpyDeviceToHost, h->st));
     HCHK(hipEventRecord(h->ev_slot[slot], h->st));
     return HELM_OK;
 }
@@ -360,7 +362,8 @@ int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int le
     HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
     HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
     HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
-    HCHK(launch_reduce(h->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, h->sig + j1, h->st));
+    HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, 2 * PSTRIDE + 1,
+                             h->hpub_dev + slot * HBUF, h->st));
     if (readback) RCHK(step_readback(h, slot));
     return HELM_OK;
 }
@@ -368,7 +371,7 @@ int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int le
 int arnoldi_finish(helm_ctx *h, int j1, int slot, zc *col, double *hn)
 {
     HCHK(hipEventSynchronize(h->ev_slot[slot]));
-    const cd *hp = h->hpin + slot * HBUF;
+    const cd *hp = h->hpub + slot * HBUF;
     bool reorth = false;
     for (int i = 0; i < j1; i++) {
         col[i] = zc(hp[i].x + hp[PSTRIDE + i].x, hp[i].y + hp[PSTRIDE + i].y);
@@ -558,7 +561,8 @@ int arnoldi_lazy_enqueue32(helm_ctx *h, size_t n, int j1, int slot, bool readbac
     HCHK(launch_mdot32(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
     HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
     HCHK(launch_mupdate32(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
-    HCHK(launch_reduce(h->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, h->sig + j1, h->st));
+    HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, 2 * PSTRIDE + 1,
+                             h->hpub_dev + slot * HBUF, h->st));
     if (readback) RCHK(step_readback(h, slot));
     return HELM_OK;
 }
@@ -1677,6 +1681,7 @@ void release(helm_ctx *h)
     dfree(h->w2);
     dfree(h->r);
     if (h->hpin) (void)hipHostFree(h->hpin);
+    if (h->hpub) (void)hipHostFree(h->hpub);
     dfree(h->sig);
     for (auto e : h->ev_slot)
         if (e) (void)hipEventDestroy(e);
@@ -1809,6 +1814,15 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (!rc && hipHostMalloc((void **)&h->hpin, PIN_TOTAL * sizeof(cd)) != hipSuccess) {
         h->hpin = nullptr;
         rc = HELM_ENOMEM;
+    }
+    if (!rc && hipHostMalloc((void **)&h->hpub, 2 * HBUF * sizeof(cd),
+                             hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        h->hpub = nullptr;
+        rc = HELM_ENOMEM;
+    }
+    if (!rc && hipHostGetDevicePointer((void **)&h->hpub_dev, h->hpub, 0) != hipSuccess) {
+        h->hpub_dev = nullptr;
+        rc = HELM_EHIP;
     }
     for (int q = 0; q < 2 && !rc; q++)
         if (hipEventCreateWithFlags(&h->ev_slot[q], hipEventDisableTiming) != hipSuccess) {

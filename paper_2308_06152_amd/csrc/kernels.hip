@@ -2072,7 +2072,8 @@ __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int
                                                 cd *__restrict__ out, int mode,
                                                 const cd *__restrict__ cond, int jcond,
                                                 const cd *__restrict__ sig, int nsig,
-                                                cd *__restrict__ sig_out, Batch bt)
+                                                cd *__restrict__ sig_out, Batch bt,
+                                                const cd *pub_src, int pub_n, cd *pub_dst)
 {
     if (skip_rhs(bt)) return;
     {
@@ -2110,6 +2111,13 @@ __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int
             if (sig_out) sig_out[0] = make_double2(nr > 0.0 ? 1.0 / nr : 0.0, 0.0);
         }
     }
+    if (pub_dst) {
+        // publish pub_src[0, pub_n) (written by earlier kernels, and out[i]
+        // just above) to host-visible memory
+        __syncthreads();
+        for (int q = threadIdx.x; q < pub_n; q += 256) pub_dst[q] = pub_src[q];
+        __threadfence_system();
+    }
 }
 
 hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, const cd *cond,
@@ -2117,7 +2125,15 @@ hipError_t launch_reduce(const cd *part, int nblk, int m, cd *out, int mode, con
                          Batch bt)
 {
     k_reduce<<<dim3(m, bt.B), 256, 0, st>>>(part, nblk, out, mode, cond, jcond, sig, nsig, sig_out,
-                                            bt);
+                                            bt, nullptr, 0, nullptr);
+    HD_LAUNCH_CHECK();
+}
+
+hipError_t launch_norm_publish(const cd *part, int nblk, cd *out, cd *sig_out,
+                               const cd *pub_src, int pub_n, cd *pub_dst, hipStream_t st)
+{
+    k_reduce<<<1, 256, 0, st>>>(part, nblk, out, 2, nullptr, 0, nullptr, 0, sig_out, Batch{},
+                                pub_src, pub_n, pub_dst);
     HD_LAUNCH_CHECK();
 }
 
