@@ -342,8 +342,9 @@ int step_readback(helm_ctx *h, int slot)
 // u_i with v_i = sig[i] u_i.  The new vector w = A z already sits in V[j1];
 // it is orthogonalised in place (same conditional second pass as above) and
 // sig[j1] = 1/||w'|| is stored, so no scaling pass is needed.  Everything is
-// enqueued; the scalars are copied to pinned slot `slot` and ev_slot[slot]
-// is recorded.  arnoldi_finish() waits for that event.
+// enqueued; the norm reduction also writes the step's scalars to the host
+// slot hpub + slot * HBUF, and (with readback) ev_slot[slot] is recorded.
+// arnoldi_finish() waits for that event.
 int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int lev, int slot,
                          bool readback = true)
 {
@@ -528,8 +529,9 @@ int coarse_apply(helm_ctx *h, const cd *x, const cd *b, cd *y)
 }
 
 // One inner Arnoldi step j, enqueued: z = V(v_j), w = A_2h z written into
-// basis slot j+1, then the lazily normalised orthogonalisation (and, with
-// readback, the copy of its scalars to pinned slot `slot`).
+// basis slot j+1, then the lazily normalised orthogonalisation, whose last
+// kernel writes the step's scalars to host slot `slot` (and, with readback,
+// the slot's event).
 int inner_step_enqueue(helm_ctx *h, int j, int slot, bool readback = true)
 {
     const size_t nc = h->L[1].n();
@@ -577,10 +579,11 @@ int inner_step_enqueue32(helm_ctx *h, int j, int slot, bool readback = true)
 
 // Inner step j through a HIP graph: its kernels (they depend on j only: the
 // basis slots, the Gram-Schmidt length) are captured on first use and
-// replayed from then on, one launch instead of about twenty.  The scalar
-// read-back and its event stay ordinary stream work, so the graph holds
-// kernel nodes only.  Off while kernel timing is on; a failed capture turns
-// graphs off for this context and the step is launched directly.
+// replayed from then on, one launch instead of about twenty.  The slot's
+// event stays ordinary stream work (the scalars reach the host slot from the
+// step's last kernel), so the graph holds kernel nodes only.  Off while
+// kernel timing is on; a failed capture turns graphs off for this context and
+// the step is launched directly.
 int inner_step_run(helm_ctx *h, int j, int slot)
 {
     const bool b32 = h->basis32;
