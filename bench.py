@@ -48,6 +48,9 @@ def parse():
                     help="layered: 1 = one batched solve of all sources, 0 = one after another")
     ap.add_argument("--graphs", type=int, choices=[0, 1], default=0,
                     help="1 = coarse-GMRES steps replayed from captured HIP graphs")
+    ap.add_argument("--vc-tail", type=int, default=300000,
+                    help="FP64 V-cycle: largest level (nodes) whose upward pass and those of "
+                         "the levels below run fused in one launch (0 = one launch per level)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="mixed: complex64 fine-grid V-cycle and coarse-GMRES basis inside the "
                          "FP64 solve")
@@ -142,7 +145,7 @@ def adjoint_bench(a, torch, H, inputs):
     grid = (c["nx"], c["ny"], c["h"], c["h"], H.BC_SOMMERFELD)
     opts = dict(coarse_op=H.COARSE_REDGLK2, coarse_mode=H.CMODE_TOL, coarse_tol=0.1,
                 coarse_iters=300, coarse_restart=15, restart=20, tol=1e-6, batch=a.batch,
-                graphs=a.graphs)
+                graphs=a.graphs, vc_tail=a.vc_tail)
     src = torch.from_numpy(c["sources"]).cuda()
     rec = torch.from_numpy(c["rec"]).cuda()
     kt = (omega * torch.sqrt(torch.from_numpy(c["s_true"]))).cuda()
@@ -215,7 +218,7 @@ def main():
                  k=None if kf is None else torch.from_numpy(kf).cuda(), kconst=w.kconst,
                  coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
                  coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart, restart=w.restart,
-                 tol=w.tol, precision=prec, batch=a.batch, graphs=a.graphs)
+                 tol=w.tol, precision=prec, batch=a.batch, graphs=a.graphs, vc_tail=a.vc_tail)
     nrhs = w.nsrc if w.model == "layered" else 1
     b = torch.from_numpy(w.sources() if nrhs > 1 else w.rhs()).cuda()
     x = torch.zeros_like(b)
@@ -267,7 +270,7 @@ def main():
             "krylov": f"FGMRES({w.restart}) to {w.tol:g}",
             "coarse_solve": f"GMRES({w.coarse_restart}) to {w.coarse_tol:g}",
             "outer_iters": last["outer_iters"], "inner_iters_total": last["inner_iters_total"],
-            "relres": last["relres"], "graphs": bool(a.graphs),
+            "relres": last["relres"], "graphs": bool(a.graphs), "vc_tail": a.vc_tail,
             **({"nrhs": nrhs, "batched": bool(a.batch),
                 "outer_iters_max": max(i["outer_iters"] for i in infos[-1]),
                 "inner_iters_sum": sum(i["inner_iters_total"] for i in infos[-1]),

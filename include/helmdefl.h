@@ -129,6 +129,19 @@ typedef struct {
                                 directly).  Results are identical either way; on
                                 MI355X the replay measured no faster, the cost of
                                 each dependent kernel being on the device side. */
+    int vc_tail;             /* >0 (default 300000): in the FP64 V-cycle of a
+                                single right-hand side, the levels below the
+                                cycle's top level run fused: the downward passes
+                                of the last three levels above the coarsest in
+                                one launch, and the upward passes of the levels
+                                with at most this many nodes (6 at most) in
+                                another, each keeping the intermediate levels
+                                on-chip (at least two levels each, else one
+                                launch per level); 0 = one launch per level.
+                                Both evaluate the same expressions in the same
+                                order (bit-identical results with a constant k;
+                                with a variable k the per-node coefficients may
+                                differ in the last bit). */
 } helm_opts;
 
 /* Per right-hand side result of helm_solve. */

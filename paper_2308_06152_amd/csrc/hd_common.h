@@ -154,6 +154,22 @@ hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, cons
                           const cd *rs, cd *rc, hipStream_t st);
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
                         const cd *rs, const cd *ec, cd *out, int accumulate, hipStream_t st);
+// The upward passes of levels l .. l + nt - 1 (the last one above the
+// coarsest) in one launch, FP64: levs[k] = level l + k, levs[nt] = the
+// coarsest; r[k] = level l + k's right-hand side, xc = the coarsest solution;
+// out = the correction of level l.  Equal to nt launches of launch_vc_up with
+// no scale, accumulation or Z v2.  1 <= nt <= VC_TAIL_MAXLEV.
+constexpr int VC_TAIL_MAXLEV = 6;
+// The downward passes of the last nd levels above the coarsest in one launch,
+// FP64: levs[j] = level Lc - j (levs[0] the coarsest), r = level Lc - nd's
+// right-hand side; out[j] = the right-hand side of level Lc - j, for j < nd
+// (out[0]: the coarsest).  Equal to nd launches of launch_vc_down with no
+// scale.  1 <= nd <= VC_DTAIL_MAXLEV.
+constexpr int VC_DTAIL_MAXLEV = 3;
+hipError_t launch_vc_down_tail(int nd, const Lev *levs, const cd *r, cd *const *out, cd s,
+                               double omega, hipStream_t st);
+hipError_t launch_vc_up_tail(int nt, const Lev *levs, const cd *const *r, const cd *xc, cd *out,
+                             cd s, double omega, hipStream_t st);
 // x = Minv r on the coarsest level (dense inverse, n x n, row major).
 hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st,
                            Batch bt = Batch{});

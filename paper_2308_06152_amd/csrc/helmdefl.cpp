@@ -437,6 +437,64 @@ int vcycle_mixed(helm_ctx *h, const cd *r, cd *z, int accumulate, const cd *v2)
     return HELM_OK;
 }
 
+// The downward passes of the levels below level `top`: the last ones above
+// the coarsest (VC_DTAIL_MAXLEV at most, two at least, with opts.vc_tail > 0)
+// in one fused launch.  Returns the first level whose downward pass is fused
+// (its right-hand side must be in place before vc_down_tail), or the
+// coarsest level when none is.
+int dtail_start(const helm_ctx *h, int top)
+{
+    const int Lc = h->nlev - 1;
+    if (h->o.vc_tail <= 0) return Lc;
+    const int nd = std::min(VC_DTAIL_MAXLEV, Lc - top - 1);
+    if (nd < 2 || (double)h->L[Lc - nd].n() > (double)h->o.vc_tail) return Lc;
+    return Lc - nd;
+}
+
+int vc_down_tail(helm_ctx *h, int ld)
+{
+    const int Lc = h->nlev - 1, nd = Lc - ld;
+    Lev levs[VC_DTAIL_MAXLEV + 1];
+    cd *out[VC_DTAIL_MAXLEV];
+    double by = 16.0 * h->L[ld].n();
+    for (int j = 0; j <= nd; j++) levs[j] = h->lev(Lc - j);
+    for (int j = 0; j < nd; j++) {
+        out[j] = h->L[Lc - j].r;
+        by += 16.0 * h->L[Lc - j].n();
+    }
+    Timed tm(h, HELM_K_VC_DOWN, ld, by);
+    HCHK(launch_vc_down_tail(nd, levs, h->L[ld].r, out, h->shift, h->o.omega, h->st));
+    return HELM_OK;
+}
+
+// The upward passes of the levels below level `top`, from the coarsest up:
+// the small ones (at most opts.vc_tail nodes each, VC_TAIL_MAXLEV at most,
+// two at least) in one fused launch.  *next = the highest level whose upward
+// pass is still to run, level by level.
+int vc_up_tail(helm_ctx *h, int top, int *next)
+{
+    const int Lc = h->nlev - 1;
+    *next = Lc - 1;
+    if (h->o.vc_tail <= 0) return HELM_OK;
+    int lt = top + 1;
+    while (lt < Lc && (double)h->L[lt].n() > (double)h->o.vc_tail) lt++;
+    lt = std::max(lt, Lc - VC_TAIL_MAXLEV);
+    const int nt = Lc - lt;
+    if (nt < 2) return HELM_OK;
+    Lev levs[VC_TAIL_MAXLEV + 1];
+    const cd *rr[VC_TAIL_MAXLEV];
+    double by = 16.0 * h->L[lt].n() + 16.0 * h->L[Lc].n();
+    for (int k = 0; k <= nt; k++) levs[k] = h->lev(lt + k);
+    for (int k = 0; k < nt; k++) {
+        rr[k] = h->L[lt + k].r;
+        by += 16.0 * h->L[lt + k].n();
+    }
+    Timed tm(h, HELM_K_VC_UP, lt, by);
+    HCHK(launch_vc_up_tail(nt, levs, rr, h->L[Lc].x, h->L[lt].x, h->shift, h->o.omega, h->st));
+    *next = lt - 1;
+    return HELM_OK;
+}
+
 // z (+)= V-cycle(r) starting on level l0; on level 0 the last pass may add
 // Z v2 (v2 on level 1).  From level 0 with the mixed-precision option the
 // cycle runs in complex64.
@@ -459,14 +517,18 @@ int vcycle(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2
         return HELM_OK;
     }
     const cd *rin = r;
-    for (int l = l0; l < Lc; l++) {
+    const int ld = dtail_start(h, l0);
+    for (int l = l0; l < ld; l++) {
         Timed tm(h, HELM_K_VC_DOWN, l, 16.0 * h->L[l].n() + 16.0 * h->L[l + 1].n());
         HCHK(launch_vc_down(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, rin,
                             l == l0 ? rs : nullptr, h->L[l + 1].r, h->st));
         rin = h->L[l + 1].r;
     }
+    if (ld < Lc) RCHK(vc_down_tail(h, ld));
     HCHK(launch_coarsest(h->ncoarsest, h->cinv, h->L[Lc].r, h->L[Lc].x, h->st));
-    for (int l = Lc - 1; l >= l0; l--) {
+    int lup;
+    RCHK(vc_up_tail(h, l0, &lup));
+    for (int l = lup; l >= l0; l--) {
         const bool top = l == l0;
         const cd *rl = top ? r : h->L[l].r;
         cd *out = top ? z : h->L[l].x;
@@ -490,13 +552,17 @@ int vcycle32(helm_ctx *h, const cf *r, cd *z, const cd *rs)
         Timed tm(h, HELM_K_VC_DOWN, 1, 8.0 * h->L[1].n() + 16.0 * h->L[2].n());
         HCHK(launch_vc_down(h->lev(1), h->lev(2), h->shift, h->o.omega, r, rs, h->L[2].r, h->st));
     }
-    for (int l = 2; l < Lc; l++) {
+    const int ld = dtail_start(h, 1);
+    for (int l = 2; l < ld; l++) {
         Timed tm(h, HELM_K_VC_DOWN, l, 16.0 * h->L[l].n() + 16.0 * h->L[l + 1].n());
         HCHK(launch_vc_down(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, h->L[l].r, nullptr,
                             h->L[l + 1].r, h->st));
     }
+    if (ld < Lc) RCHK(vc_down_tail(h, ld));
     HCHK(launch_coarsest(h->ncoarsest, h->cinv, h->L[Lc].r, h->L[Lc].x, h->st));
-    for (int l = Lc - 1; l >= 2; l--) {
+    int lup;
+    RCHK(vc_up_tail(h, 1, &lup));
+    for (int l = lup; l >= 2; l--) {
         Timed tm(h, HELM_K_VC_UP, l, 32.0 * h->L[l].n() + 16.0 * h->L[l + 1].n());
         HCHK(launch_vc_up(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, h->L[l].r, nullptr,
                           h->L[l + 1].x, h->L[l].x, 0, nullptr, h->zho, h->st));
@@ -1721,6 +1787,7 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (o.outer < HELM_OUTER_FGMRES || o.outer > HELM_OUTER_GMRES_LEFT) return HELM_EINVAL;
     if (o.batch != 0 && o.batch != 1) return HELM_EINVAL;
     if (o.graphs != 0 && o.graphs != 1) return HELM_EINVAL;
+    if (o.vc_tail < 0) return HELM_EINVAL;
     if (o.coarse_mode != HELM_CMODE_FIXED && o.coarse_mode != HELM_CMODE_TOL) return HELM_EINVAL;
     if (o.coarse_iters < 1 || o.coarse_restart < 1 || o.coarse_restart > MAX_RESTART)
         return HELM_EINVAL;
@@ -1881,6 +1948,7 @@ int helm_opts_default(helm_opts *o)
     o->outer = HELM_OUTER_FGMRES;
     o->batch = 1;
     o->graphs = 0;
+    o->vc_tail = 300000;
     return HELM_OK;
 }
 

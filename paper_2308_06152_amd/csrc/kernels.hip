@@ -497,6 +497,190 @@ hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, cons
     return vc_down_t<float, double>(Lf, Lc, s, omega, r, rs, rc, st, Batch{});
 }
 
+// (q / w, q % w) for 0 <= q < 2^12, 0 < w < 2^8 by a float reciprocal: the
+// quotient's fraction is at least 1/(2w) from an integer, far above the error
+struct Div {
+    float rw;
+    int w;
+    __device__ explicit Div(int w_) : rw(1.0f / (float)w_), w(w_) {}
+    __device__ int quo(int q) const { return (int)(((float)q + 0.5f) * rw); }
+};
+
+// ------------------------------------------------------------------------
+// The downward passes of the last nd <= 3 levels above the coarsest fused
+// into one launch.  A block owns a DT_C x DT_C tile [A, B] of the coarsest
+// level and computes its right-hand side from level Lc - nd's: the tile needs
+// r1 of level Lc - 1 on [2A-1, 2B+1], hence x1 and r there grown by one node,
+// so level Lc - j contributes its r on G_j = [2^j A - (2^(j+1) - 2),
+// 2^j B + (2^(j+1) - 2)] (37 x 37 nodes at j = 3).  The block loads r on G_nd
+// once and computes every stage in LDS: x1 on G_j, r1 on G_j shrunk by one
+// node, full weighting on G_(j-1), each in k_vc_down's expressions and order
+// (no right-hand side scale), with 0 outside the grid and at nodes that are
+// not unknowns, as k_vc_down's tile and output hold.  Level Lc - j + 1's
+// right-hand side is also needed by the upward pass: each block writes the
+// nodes it owns there, [2^(j-1) A, 2^(j-1) (B+1) - 1] per axis (a partition of
+// the level; the last tile's range runs past the grid's end).
+// ------------------------------------------------------------------------
+constexpr int DT_C = 2;                        // coarsest nodes per tile side
+constexpr int DT_G = 8 * (DT_C - 1) + 29;      // side of G_3 (37)
+constexpr int DT_N = DT_G * DT_G;              // nodes of G_3
+constexpr int DT_T = 512;                      // threads per block
+constexpr int DT_S = (DT_N + DT_T - 1) / DT_T;  // r loads per thread
+
+struct DTailArgs {
+    int nd;                         // fused levels Lc - nd .. Lc - 1
+    int tiles_x;                    // tiles per row of the coarsest level
+    Lev L[VC_DTAIL_MAXLEV + 1];     // L[j]: level Lc - j (L[0]: the coarsest)
+    Smooth<double> c[VC_DTAIL_MAXLEV + 1];  // c[j]: level Lc - j, j >= 1
+    const cd *r;                    // right-hand side of level Lc - nd
+    cd *out[VC_DTAIL_MAXLEV];       // out[j]: right-hand side of level Lc - j, j < nd
+};
+
+template <bool VARK>
+__global__ __launch_bounds__(DT_T) void k_vc_down_tail(DTailArgs a, cd s, double omega)
+{
+    __shared__ cd rb[DT_N];    // r on G_j
+    __shared__ cd x1b[DT_N];   // x1 on G_j, then r1 on G_j shrunk by one node
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int nd = a.nd;
+    const int A = (t % a.tiles_x) * DT_C, Ay = (t / a.tiles_x) * DT_C;
+    // ---- r of level Lc - nd on G_nd (masked like k_vc_down's loads)
+    {
+        const Lev &L = a.L[nd];
+        const int lox = (A << nd) - ((2 << nd) - 2), loy = (Ay << nd) - ((2 << nd) - 2);
+        const int w = (DT_C - 1) * (1 << nd) + (4 << nd) - 3;
+        const Div d(w);
+        cd v[DT_S];
+        double m[DT_S];
+#pragma unroll
+        for (int sl = 0; sl < DT_S; sl++) {
+            const int q = threadIdx.x + DT_T * sl;
+            const int qy = d.quo(q);
+            const int fi = lox + q - qy * w, fj = loy + qy;
+            const bool in = q < w * w && fi >= 0 && fi < L.nx && fj >= 0 && fj < L.ny &&
+                            unknown(L, fi, fj);
+            v[sl] = a.r[in ? (size_t)fj * L.nx + fi : 0];
+            m[sl] = in ? 1.0 : 0.0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int sl = 0; sl < DT_S; sl++) {
+            const int q = threadIdx.x + DT_T * sl;
+            if (q < w * w) rb[q] = cscal(m[sl], v[sl]);
+        }
+    }
+    __syncthreads();
+    for (int j = nd; j >= 1; j--) {
+        const Lev &L = a.L[j];
+        const Lev &Lc = a.L[j - 1];
+        const Smooth<double> &c = a.c[j];
+        const int lox = (A << j) - ((2 << j) - 2), loy = (Ay << j) - ((2 << j) - 2);
+        const int w = (DT_C - 1) * (1 << j) + (4 << j) - 3;
+        // x1 = omega D^-1 r on G_j
+        {
+            const Div d(w);
+            for (int q = threadIdx.x; q < w * w; q += DT_T) {
+                const int qy = d.quo(q);
+                const int fi = lox + q - qy * w, fj = loy + qy;
+                cd x = czero();
+                cd ap, wv;
+                double aw, ae, as, an;
+                if (fi >= 0 && fi < L.nx && fj >= 0 && fj < L.ny &&
+                    node_coef<VARK, double>(L, s, omega, c, fi, fj, ap, wv, aw, ae, as, an))
+                    x = cmul(wv, rb[q]);
+                x1b[q] = x;
+            }
+        }
+        __syncthreads();
+        // r1 = r - M x1 on G_j shrunk by one node (kept in registers until
+        // every thread has read x1)
+        const int w1 = w - 2;
+        constexpr int NR = (DT_G - 2) * (DT_G - 2) / DT_T + 1;
+        cd r1[NR];
+        {
+            const Div d(w1);
+#pragma unroll
+            for (int sl = 0; sl < NR; sl++) {
+                const int q = threadIdx.x + DT_T * sl;
+                r1[sl] = czero();
+                if (q >= w1 * w1) continue;
+                const int qy = d.quo(q);
+                const int ii = q - qy * w1 + 1, jj = qy + 1;
+                const int fi = lox + ii, fj = loy + jj;
+                const int cxy = jj * w + ii;
+                cd ap, wv;
+                double aw, ae, as, an;
+                if (fi >= 0 && fi < L.nx && fj >= 0 && fj < L.ny &&
+                    node_coef<VARK, double>(L, s, omega, c, fi, fj, ap, wv, aw, ae, as, an)) {
+                    cd mm = cmul(ap, x1b[cxy]);
+                    caxpy(mm, aw, x1b[cxy - 1]);
+                    caxpy(mm, ae, x1b[cxy + 1]);
+                    caxpy(mm, as, x1b[cxy - w]);
+                    caxpy(mm, an, x1b[cxy + w]);
+                    r1[sl] = csub(rb[cxy], mm);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int sl = 0; sl < NR; sl++) {
+            const int q = threadIdx.x + DT_T * sl;
+            if (q < w1 * w1) x1b[q] = r1[sl];
+        }
+        __syncthreads();
+        // full weighting on G_(j-1) = [lox/2 + 1, ...]: coarse node (I, J) sits
+        // at fine (2I, 2J) = r1 entry (2(I - clo) + 1, 2(J - cloy) + 1)
+        {
+            const int clox = (lox + 2) >> 1, cloy = (loy + 2) >> 1;
+            const int cw = (w - 3) >> 1;
+            const int ox = A << (j - 1), oy = Ay << (j - 1);  // owned range
+            const int on = DT_C << (j - 1);
+            const Div d(cw);
+            for (int q = threadIdx.x; q < cw * cw; q += DT_T) {
+                const int qy = d.quo(q);
+                const int I = clox + q - qy * cw, J = cloy + qy;
+                const bool ing = I >= 0 && I < Lc.nx && J >= 0 && J < Lc.ny;
+                cd v = czero();
+                if (ing && unknown(Lc, I, J)) {
+                    const int aa = 2 * (I - clox) + 1, bb = 2 * (J - cloy) + 1;
+                    const cd *rr = x1b + bb * w1 + aa;
+                    cd ce = cscal(4.0, rr[0]);
+                    cd e = cadd(cadd(rr[-1], rr[1]), cadd(rr[-w1], rr[w1]));
+                    cd dd = cadd(cadd(rr[-w1 - 1], rr[-w1 + 1]), cadd(rr[w1 - 1], rr[w1 + 1]));
+                    v = cscal(1.0 / 16.0, cadd(cadd(ce, cscal(2.0, e)), dd));
+                }
+                rb[q] = v;
+                if (ing && I >= ox && I < ox + on && J >= oy && J < oy + on)
+                    a.out[j - 1][(size_t)J * Lc.nx + I] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_vc_down_tail(int nd, const Lev *levs, const cd *r, cd *const *out, cd s,
+                               double omega, hipStream_t st)
+{
+    if (nd < 1 || nd > VC_DTAIL_MAXLEV) return hipErrorInvalidValue;
+    DTailArgs a;
+    a.nd = nd;
+    a.tiles_x = cdiv(levs[0].nx, DT_C);
+    bool vark = false;
+    for (int j = 0; j <= nd; j++) {
+        a.L[j] = levs[j];
+        vark |= levs[j].k != nullptr;
+        a.c[j] = j ? smooth_consts<double>(levs[j], s, omega) : Smooth<double>{};
+    }
+    for (int j = 0; j < nd; j++) a.out[j] = out[j];
+    a.r = r;
+    const int g = a.tiles_x * cdiv(levs[0].ny, DT_C);
+    if (vark)
+        k_vc_down_tail<true><<<g, DT_T, 0, st>>>(a, s, omega);
+    else
+        k_vc_down_tail<false><<<g, DT_T, 0, st>>>(a, s, omega);
+    HD_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------------------------------
 // V-cycle, upward pass on a level (fused):
 //   x2 = omega D^{-1} r + P ec      (the pre-smoothed iterate, recomputed,
@@ -686,6 +870,205 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
         if (accumulate) v = cadd(v, oold[rr]);
         out[p] = v;
     }
+}
+
+// ------------------------------------------------------------------------
+// The upward passes of the small levels fused into one launch: a block owns a
+// VT_TX x VT_TY tile of level lt and computes the corrections of every level
+// from the coarsest up to lt on the nodes its tile needs, in LDS.  Level k's
+// output region R_k (k = 0 is level lt) needs x2 on R_k grown by one node, so
+// the correction of level k+1 on R_{k+1} = [floor((a-1)/2), ceil((b+1)/2)]
+// per axis; the regions shrink by about half per level (32 x 16, 18 x 10,
+// 11 x 7, 7 x 5, ...), so the redundant work below level lt is small.  Each
+// stage is k_vc_up's arithmetic, in its order (r from the level's buffer, no
+// right-hand side scale, no accumulation, no Z v2), and nodes outside the grid
+// or not unknowns hold 0, as k_vc_up's output there and its masked ec tile do.
+// The kernel is latency bound (a few thousand nodes per block over several
+// dependent stages), so the loads are pipelined: thread q of a stage's grown
+// region loads r (and k) there into registers one stage ahead, uses them for
+// x2 and leaves them in LDS for the smoothing of the same nodes.
+// ------------------------------------------------------------------------
+constexpr int VT_TX = 32, VT_TY = 16;                       // tile of level lt
+constexpr int VT_E = (VT_TX / 2 + 2) * (VT_TY / 2 + 2);     // largest region below lt
+constexpr int VT_X = (VT_TX + 2) * (VT_TY + 2);             // largest x2 region (level lt)
+constexpr int VT_T = 256;                                   // threads per block
+constexpr int VT_S = (VT_X + VT_T - 1) / VT_T;              // x2 nodes per thread
+
+struct TailArgs {
+    int nt;                         // levels lt .. lt + nt - 1 (the last is above the coarsest)
+    int tiles_x;
+    Lev L[VC_TAIL_MAXLEV + 1];      // L[k]: level lt + k; L[nt]: the coarsest level
+    Smooth<double> c[VC_TAIL_MAXLEV];
+    const cd *r[VC_TAIL_MAXLEV];    // right-hand side of level lt + k
+    const cd *xc;                   // coarsest solution
+    cd *out;                        // correction of level lt
+};
+
+
+template <bool VARK>
+__global__ __launch_bounds__(VT_T) void k_vc_up_tail(TailArgs a, cd s, double omega)
+{
+    __shared__ cd x2b[VT_X];
+    __shared__ cd rbuf[VT_X];                 // r on the stage's grown region
+    __shared__ double kbuf[VARK ? VT_X : 1];  // k there (variable k)
+    __shared__ cd eb[2][VT_E];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int nt = a.nt;
+    int ia[VC_TAIL_MAXLEV + 1], ib[VC_TAIL_MAXLEV + 1], ja[VC_TAIL_MAXLEV + 1],
+        jb[VC_TAIL_MAXLEV + 1];
+    ia[0] = (t % a.tiles_x) * VT_TX;
+    ib[0] = ia[0] + VT_TX - 1;
+    ja[0] = (t / a.tiles_x) * VT_TY;
+    jb[0] = ja[0] + VT_TY - 1;
+#pragma unroll
+    for (int k = 0; k < VC_TAIL_MAXLEV; k++) {
+        ia[k + 1] = (ia[k] - 1) >> 1;
+        ib[k + 1] = (ib[k] + 2) >> 1;
+        ja[k + 1] = (ja[k] - 1) >> 1;
+        jb[k + 1] = (jb[k] + 2) >> 1;
+    }
+    // r (and k) of level k's grown region at this thread's nodes q = tid + VT_T sl,
+    // masked to 0 outside the grid (loads unconditional, from a valid address)
+    cd rn[VT_S];
+    double kn[VT_S], mn[VT_S];
+    auto load_level = [&](int k) {
+        const Lev &L = a.L[k];
+        const cd *__restrict__ r = a.r[k];
+        const int xw = ib[k] - ia[k] + 3, xh = jb[k] - ja[k] + 3;
+        const Div d(xw);
+#pragma unroll
+        for (int sl = 0; sl < VT_S; sl++) {
+            const int q = threadIdx.x + VT_T * sl;
+            const int qy = d.quo(q);
+            const int fi = ia[k] - 1 + q - qy * xw, fj = ja[k] - 1 + qy;
+            const bool in = q < xw * xh && fi >= 0 && fi < L.nx && fj >= 0 && fj < L.ny;
+            const size_t p = in ? (size_t)fj * L.nx + fi : 0;
+            rn[sl] = r[p];
+            if (VARK) kn[sl] = L.k[p];
+            mn[sl] = in ? 1.0 : 0.0;
+        }
+    };
+    {  // the coarsest solution on R_nt, with the first stage's r
+        const Lev &Lc = a.L[nt];
+        const int w = ib[nt] - ia[nt] + 1, hh = jb[nt] - ja[nt] + 1;
+        const Div d(w);
+        constexpr int NE = (VT_E + VT_T - 1) / VT_T;
+        cd ce[NE];
+        double cm[NE];
+#pragma unroll
+        for (int sl = 0; sl < NE; sl++) {
+            const int q = threadIdx.x + VT_T * sl;
+            const int qy = d.quo(q);
+            const int I = ia[nt] + q - qy * w, J = ja[nt] + qy;
+            const bool in = q < w * hh && I >= 0 && I < Lc.nx && J >= 0 && J < Lc.ny &&
+                            unknown(Lc, I, J);
+            ce[sl] = a.xc[in ? (size_t)J * Lc.nx + I : 0];
+            cm[sl] = in ? 1.0 : 0.0;
+        }
+        load_level(nt - 1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int sl = 0; sl < NE; sl++) {
+            const int q = threadIdx.x + VT_T * sl;
+            if (q < w * hh) eb[nt & 1][q] = cscal(cm[sl], ce[sl]);
+        }
+    }
+    __syncthreads();
+    for (int k = nt - 1; k >= 0; k--) {
+        const Lev &L = a.L[k];
+        const Smooth<double> &c = a.c[k];
+        const cd *ec = eb[(k + 1) & 1];
+        const int ew = ib[k + 1] - ia[k + 1] + 1;
+        const int xw = ib[k] - ia[k] + 3, xh = jb[k] - ja[k] + 3;
+        // x2 = omega D^-1 r + P e on R_k grown by one node (this thread's nodes)
+        {
+            const Div d(xw);
+#pragma unroll
+            for (int sl = 0; sl < VT_S; sl++) {
+                const int q = threadIdx.x + VT_T * sl;
+                if (q >= xw * xh) break;
+                const int qy = d.quo(q);
+                const int fi = ia[k] - 1 + q - qy * xw, fj = ja[k] - 1 + qy;
+                const cd rv = cscal(mn[sl], rn[sl]);
+                cd x = czero();
+                cd ap, wv;
+                double aw, ae, as, an;
+                if (fi >= 0 && fi < L.nx && fj >= 0 && fj < L.ny &&
+                    node_coef_k<VARK, double>(L, s, omega, c, fi, fj, VARK ? kn[sl] : L.kc, ap,
+                                              wv, aw, ae, as, an)) {
+                    const int ca = (fi >> 1) - ia[k + 1], cb = (fj >> 1) - ja[k + 1];
+                    cd p = ec[cb * ew + ca];
+                    if (fi & 1) p = cscal(0.5, cadd(p, ec[cb * ew + ca + 1]));
+                    if (fj & 1) {
+                        cd p2 = ec[(cb + 1) * ew + ca];
+                        if (fi & 1) p2 = cscal(0.5, cadd(p2, ec[(cb + 1) * ew + ca + 1]));
+                        p = cscal(0.5, cadd(p, p2));
+                    }
+                    x = cadd(cmul(wv, rv), p);
+                }
+                x2b[q] = x;
+                rbuf[q] = rv;
+                if (VARK) kbuf[q] = kn[sl];
+            }
+        }
+        // the next stage's loads fly during this stage's smoothing
+        if (k > 0) load_level(k - 1);
+        __syncthreads();
+        // post-smoothing on R_k: the correction of level k
+        const int ow = xw - 2, oh = xh - 2;
+        const Div d(ow);
+        for (int q = threadIdx.x; q < ow * oh; q += VT_T) {
+            const int jj = d.quo(q), ii = q - jj * ow;
+            const int fi = ia[k] + ii, fj = ja[k] + jj;
+            const int cxy = (jj + 1) * xw + ii + 1;
+            const bool ing = fi >= 0 && fi < L.nx && fj >= 0 && fj < L.ny;
+            cd x = czero();
+            cd ap, wv;
+            double aw, ae, as, an;
+            if (ing && node_coef_k<VARK, double>(L, s, omega, c, fi, fj,
+                                                 VARK ? kbuf[cxy] : L.kc, ap, wv, aw, ae, as,
+                                                 an)) {
+                cd m = cmul(ap, x2b[cxy]);
+                caxpy(m, aw, x2b[cxy - 1]);
+                caxpy(m, ae, x2b[cxy + 1]);
+                caxpy(m, as, x2b[cxy - xw]);
+                caxpy(m, an, x2b[cxy + xw]);
+                x = cadd(x2b[cxy], cmul(wv, csub(rbuf[cxy], m)));
+            }
+            if (k == 0) {
+                if (ing) a.out[(size_t)fj * L.nx + fi] = x;
+            } else {
+                eb[k & 1][q] = x;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_vc_up_tail(int nt, const Lev *levs, const cd *const *r, const cd *xc, cd *out,
+                             cd s, double omega, hipStream_t st)
+{
+    if (nt < 1 || nt > VC_TAIL_MAXLEV) return hipErrorInvalidValue;
+    TailArgs a;
+    a.nt = nt;
+    a.tiles_x = cdiv(levs[0].nx, VT_TX);
+    bool vark = false;
+    for (int k = 0; k <= nt; k++) {
+        a.L[k] = levs[k];
+        vark |= levs[k].k != nullptr;
+    }
+    for (int k = 0; k < nt; k++) {
+        a.c[k] = smooth_consts<double>(levs[k], s, omega);
+        a.r[k] = r[k];
+    }
+    a.xc = xc;
+    a.out = out;
+    const int g = a.tiles_x * cdiv(levs[0].ny, VT_TY);
+    if (vark)
+        k_vc_up_tail<true><<<g, VT_T, 0, st>>>(a, s, omega);
+    else
+        k_vc_up_tail<false><<<g, VT_T, 0, st>>>(a, s, omega);
+    HD_LAUNCH_CHECK();
 }
 
 template <class RI, class R, class RO>

@@ -52,7 +52,7 @@ class Opts(ctypes.Structure):
                 ("x0_given", ctypes.c_int), ("force_iters", ctypes.c_int),
                 ("coarsest_nodes", ctypes.c_int), ("precision", ctypes.c_int),
                 ("outer", ctypes.c_int), ("batch", ctypes.c_int),
-                ("graphs", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("vc_tail", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

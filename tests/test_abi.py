@@ -51,6 +51,7 @@ def test_defaults_and_strerror(H):
     assert o.outer == H.OUTER_FGMRES
     assert o.batch == 1
     assert o.graphs == 0
+    assert o.vc_tail == 300000
     L = H.load()
     assert L.helm_strerror(0) == b"success"
     assert b"coarsen" in L.helm_strerror(H.HELM_EGRID)
@@ -78,7 +79,7 @@ def test_create_rejects_uncoarsenable_grids(H, nx, ny):
                                 dict(coarsest_nodes=5000), dict(precision=2),
                                 dict(precision=-1), dict(coarse_op=5), dict(coarse_op=-1),
                                 dict(outer=3), dict(outer=-1), dict(batch=2),
-                                dict(graphs=2), dict(graphs=-1)])
+                                dict(graphs=2), dict(graphs=-1), dict(vc_tail=-1)])
 def test_create_rejects_bad_options(H, kw):
     assert _create(H, 9, 9, **kw) == H.HELM_EINVAL
 

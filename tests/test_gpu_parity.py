@@ -80,7 +80,8 @@ def make_pair(H, ora, case, coarsest_nodes=1089, **kw):
                                                       "coarse_tol", "beta_re", "beta_im", "omega",
                                                       "coarse_mode", "coarse_iters", "restart",
                                                       "tol", "maxit", "force_iters",
-                                                      "precision", "outer", "batch", "graphs")}
+                                                      "precision", "outer", "batch", "graphs",
+                                                      "vc_tail")}
     kt = dev(kfield) if kfield is not None else None
     S = H.Solver(nx, ny, h, h, bc, k=kt, kconst=kconst, coarsest_nodes=coarsest_nodes, **gkw)
     return S, P
