@@ -1,7 +1,10 @@
 """Batched multi-right-hand-side path (several right-hand sides of one
 operator in one pass).  The stencil kernels run the same arithmetic per
 right-hand side as the single path, so batched V-cycles and operators equal
-the single calls bit for bit; the Krylov kernels split a batch into fewer,
+the single calls bit for bit (with a variable k, to the last bit: the single
+V-cycle fuses its small levels into kernels that compute the per-node
+coefficients themselves, where the compiler may fuse their multiply-adds
+differently); the Krylov kernels split a batch into fewer,
 larger blocks per vector, so reductions round differently and Krylov-based
 results agree with the single calls to rounding.  Everything matches the
 oracle to the usual bars.  Solves mix right-hand sides that converge at
@@ -26,7 +29,10 @@ def test_batched_vcycle_and_apply(H, ora, case):
     yb = host(S.apply(dev(r)))
     for q in range(B):
         zs = host(S.vcycle(dev(r[q])))
-        assert np.array_equal(zb[q], zs)
+        if case[4] == "var":
+            assert rel(zb[q], zs) <= 1e-14
+        else:
+            assert np.array_equal(zb[q], zs)
         assert rel(zb[q], ora.vcycle(P, r[q])) <= 1e-12
         assert rel(yb[q], ora.helm_apply(P, r[q])) <= 1e-12
 
