@@ -277,7 +277,9 @@ enum {
     HELM_K_NCLASSES = 8
 };
 /* Start timing launches of kernel class `kclass` on multigrid level `level`
- * (-1 = any level).  Resets the accumulators.  kclass < 0 disables timing. */
+ * (-1 = any level).  Resets the accumulators.  kclass < 0 disables timing.
+ * A fused V-cycle tail (opts.vc_tail) is one launch of HELM_K_VC_DOWN or
+ * HELM_K_VC_UP, filed under the highest level it covers. */
 int helm_timing_enable(helm_ctx *h, int kclass, int level);
 /* Read the accumulated launch count, summed event time (ms) and the summed
  * algorithmic HBM bytes of the timed launches (synchronises the stream). */
