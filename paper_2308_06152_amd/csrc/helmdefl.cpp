@@ -451,6 +451,9 @@ int dtail_start(const helm_ctx *h, int top)
     return Lc - nd;
 }
 
+// The fused downward passes from level ld (as dtail_start chose it) to the
+// coarsest: reads level ld's right-hand side, writes those of levels
+// ld + 1 .. Lc.
 int vc_down_tail(helm_ctx *h, int ld)
 {
     const int Lc = h->nlev - 1, nd = Lc - ld;
