@@ -55,7 +55,7 @@ enum { HELM_Z_LINEAR = 0, HELM_Z_HIGH = 1 };
  * 5.2.1); ReD-Glk2 and ReD-Glk1 (the Galerkin 5x5 stencils re-used as a
  * coarse discretisation, with ghost-point or second-order boundary rows,
  * Section 5.2.4); ReD-O2 and ReD-O4 (second- and fourth-order
- * re-discretisation, Section 5.2.2).  ReD-Glk* need hx == hy. */
+ * re-discretisation, Section 5.2.3).  ReD-Glk* need hx == hy. */
 enum {
     HELM_COARSE_GALERKIN = 0,
     HELM_COARSE_REDGLK2 = 1,
@@ -64,7 +64,7 @@ enum {
     HELM_COARSE_REDGLK1 = 4
 };
 /* Outer Krylov methods: flexible GMRES (right preconditioning, true residual
- * test; the default), GCR (right preconditioning, Section 6.4), and the
+ * test; the default), GCR (right preconditioning, Section 6.3), and the
  * paper's left-preconditioned GMRES of Algorithm 1 (restarted after
  * `restart` steps; stops on the preconditioned residual relative to ||P b||). */
 enum { HELM_OUTER_FGMRES = 0, HELM_OUTER_GCR = 1, HELM_OUTER_GMRES_LEFT = 2 };

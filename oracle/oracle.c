@@ -703,7 +703,7 @@ static cplx uval(const lvl_t *g, const cplx *u, int I, int J)
     return is_unknown(g, I, J) ? u[(size_t)J * g->nx + I] : 0;
 }
 
-/* ReD-O2 (Section 5.2.2): the fine-grid scheme re-discretised at spacing 2h
+/* ReD-O2 (Section 5.2.3): the fine-grid scheme re-discretised at spacing 2h
  * on every row. */
 static void coarse_redo2(const hier_t *H, const cplx *u, cplx *y)
 {
@@ -713,7 +713,7 @@ static void coarse_redo2(const hier_t *H, const cplx *u, cplx *y)
             y[(size_t)J * g->nx + I] = is_unknown(g, I, J) ? row_o2(g, u, I, J) : 0;
 }
 
-/* ReD-O4 (Section 5.2.2): the Laplacian by fourth-order central differences,
+/* ReD-O4 (Section 5.2.3): the Laplacian by fourth-order central differences,
  * -u'' ~ (u_{i-2} - 16 u_{i-1} + 30 u_i - 16 u_{i+1} + u_{i+2}) / (12 H^2) per
  * axis, minus k^2 u, at nodes two or more nodes inside the grid; the other
  * rows (where the wide stencil does not fit) use the second-order scheme with
@@ -1370,7 +1370,7 @@ done:
 }
 
 /* Right-preconditioned GCR(m) with the A-DEF1 preconditioner: the outer
- * method of Section 6.4 (Eisenstat, Elman and Schultz), which admits a
+ * method of Section 6.3 (Eisenstat, Elman and Schultz), which admits a
  * preconditioner that changes from step to step.  Step j: z = P r,
  * w = A z; w is made orthogonal to the earlier w_i by modified Gram-Schmidt,
  * the same combination is applied to z (so w = A z still holds), and both are

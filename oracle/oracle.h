@@ -13,15 +13,17 @@
  * in the paper's order, with no blocking or fusion.  Vectors are complex128,
  * stored as [ny][nx] with x fastest; node (i,j) is the vertex i*hx, j*hy.
  *
- * Parity status per routine (the pins live in tests/test_oracle_*.py):
+ * Parity status per routine (the pins live in tests/test_oracle.py):
  *   ora_helm_apply     pinned: Dirichlet sine-mode eigenvalues (Appendix B
  *                      eigenvalue formula), manufactured O(h^2) convergence
  *                      (Dirichlet and Sommerfeld), complex symmetry of D*A.
  *   ora_z_prolong /    pinned: printed Galerkin stencils (ReD-Glk section),
  *   ora_z_restrict     exact transpose identity, Z(x^2) = x^2 + H^2/4.
  *   ora_coarse_apply   pinned: interior rows equal the printed Galerkin
- *                      Laplacian and k^2 stencils; ReD-Glk2 boundary rows are
- *                      "parity unpinned" beyond the interior identity.
+ *                      Laplacian and k^2 stencils; ReD-Glk2 boundary-band rows
+ *                      (variable k, both boundary types, corner rows) equal the
+ *                      coefficients derived from the printed stencils and the
+ *                      ghost rules (Sections 2.1, 5.2.4, 5.2.5).
  *   ora_vcycle         pinned: exact on a 3x3 grid, transpose-symmetric for
  *                      Dirichlet, textbook multigrid contraction for k = 0.
  *   ora_coarse_solve   pinned: EXACT mode residual; TOL/FIXED against EXACT.
@@ -105,7 +107,7 @@ int ora_deflate_apply(const ora_problem *p, int mode, const double *v, double *w
 int ora_fgmres(const ora_problem *p, const double *b, double *x, int restart,
                double tol, int maxit, int force_iters, ora_info *info);
 /* Right-preconditioned GCR(restart) with the A-DEF1 preconditioner (the
- * variable-preconditioner outer method of Section 6.4). */
+ * variable-preconditioner outer method of Section 6.3). */
 int ora_gcr(const ora_problem *p, const double *b, double *x, int restart, double tol,
             int maxit, int force_iters, ora_info *info);
 /* The paper's left-preconditioned full GMRES (Algorithm 1, no restart),

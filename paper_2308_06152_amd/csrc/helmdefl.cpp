@@ -908,7 +908,7 @@ int read_norm(helm_ctx *h, double *out)
     return HELM_OK;
 }
 
-// Right-preconditioned GCR(m) (Section 6.4; the method of Eisenstat, Elman
+// Right-preconditioned GCR(m) (Section 6.3; the method of Eisenstat, Elman
 // and Schultz), preconditioner P_A-DEF1.  Step j: z = P r, w = A z; w is
 // orthogonalised against W[0..j-1] (the same Gram-Schmidt pass as the Arnoldi
 // steps, with its conditional second pass) and the same coefficients are

@@ -1841,7 +1841,7 @@ hipError_t launch_redglk2(const Lev &L, const cd *x, const cd *b, cd *y, int glk
 }
 
 // ------------------------------------------------------------------------
-// ReD-O4 coarse operator (Section 5.2.2): fourth-order central differences
+// ReD-O4 coarse operator (Section 5.2.3): fourth-order central differences
 // for the Laplacian, (u_{i-2} - 16 u_{i-1} + 30 u_i - 16 u_{i+1} + u_{i+2}) /
 // (12 H^2) per axis, minus k^2 u, at nodes two or more nodes inside the
 // grid; the other rows are the second-order 5-point rows with the boundary

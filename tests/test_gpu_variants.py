@@ -1,5 +1,5 @@
 """GPU parity of the paper's variants: the ReD-O2, ReD-O4 and ReD-Glk1
-coarse operators (Sections 5.2.2, 5.2.4), the GCR outer method (Section 6.4)
+coarse operators (Sections 5.2.3, 5.2.4), the GCR outer method (Section 6.3)
 and the left-preconditioned GMRES of Algorithm 1, against the CPU oracle.
 Bars as for the plain path: 1e-12 per operator, 1e-11 for A-DEF1 with a fixed
 inner count, outer counts within one and true residuals below tolerance for
@@ -118,7 +118,7 @@ def test_left_gmres_paper_counts_on_gpu(H, ora, cop):
     assert abs(info[0]["outer_iters"] - PAPER_65_K40[cop]) <= 2, info[0]
 
 
-# The paper's coarse-tolerance experiments (Section 6.4): APD (higher-order
+# The paper's coarse-tolerance experiments (Section 6.3): APD (higher-order
 # vectors) with ReD-Glk2, point source at the centre of the unit square,
 # Sommerfeld boundary; outer GMRES of Algorithm 1 (left preconditioning,
 # preconditioned residual to 1e-6) or GCR; coarse problem solved by

@@ -314,6 +314,184 @@ def test_redglk2_boundary_rows(ora):
     assert abs(col[4, 0] * H * H - (-2)) < 1e-12
 
 
+def _redglk2_probe_problem(ora, bc, nc=9):
+    """A ReD-Glk2 problem on an nc x nc coarse grid with a variable wavenumber
+    whose coarse values (injected from the coincident fine nodes) are all
+    distinct, so that taking k at the wrong node changes a coefficient."""
+    n = 2 * nc - 1
+    h = 1.0 / (n - 1)
+    rng = np.random.default_rng(2308061521)
+    kf = 4.0 + 6.0 * rng.random((n, n))
+    p = ora.Problem(n, n, h, h, bc=bc, k=kf, coarse_op=ora.COARSE_REDGLK2)
+    return p, kf[::2, ::2], 2 * h
+
+
+def _dense_coarse(ora, p, nc):
+    """Columns of A_2h by probing the oracle with unit vectors."""
+    A = np.zeros((nc * nc, nc * nc), complex)
+    for q in range(nc * nc):
+        e = np.zeros(nc * nc, complex)
+        e[q] = 1
+        A[:, q] = ora.coarse_apply(p, e.reshape(nc, nc)).ravel()
+    return A
+
+
+def _redglk2_expected_row(I, J, kc, H, nc, bc):
+    """Row (I, J) of ReD-Glk2 derived from the paper, written as coefficients.
+
+    Section 5.2.4 applies the printed 5x5 stencils (LAP / (256 H^2) and
+    K2 k^2 / 64^2, with k of each stencil node) at the second boundary layer.
+    A stencil node outside the grid is a ghost with wavenumber 0, so only its
+    LAP weight enters, and the ghost value is eliminated:
+      Sommerfeld (eq. GhostPoint at spacing H, k of the boundary node b):
+        u_ghost = u_inward + 2 i H k_b u_b
+      Dirichlet (eq. DirchletGhostPoint): u_b = (u_ghost + u_inward) / 2
+      Corner ghost (outside in x and y; the corner rule of Section 5.2.5):
+        the mean of the two single-direction ghosts next to it.
+    Returns {(Ii, Jj): coefficient} over grid nodes.
+    """
+    g = _read_matrices(os.path.join(GOLD, "glk_stencils.txt"))
+    coef = {}
+
+    def add(node, w):
+        coef[node] = coef.get(node, 0) + w
+
+    def edge_ghost(b, inward, L):
+        # coefficients of the ghost beyond boundary node b, times the weight L
+        if bc == 1:
+            add(inward, L)
+            add(b, L * 2j * H * kc[b[1], b[0]])
+        else:
+            add(b, 2 * L)
+            add(inward, -L)
+
+    def clamp(i):
+        return min(max(i, 0), nc - 1)
+
+    def inward(i):
+        return 1 if i < 0 else nc - 2
+
+    for dJ in range(-2, 3):
+        for dI in range(-2, 3):
+            L = g["LAP"][dJ + 2, dI + 2] / (256 * H * H)
+            Kw = g["K2"][dJ + 2, dI + 2] / 4096
+            Ii, Jj = I + dI, J + dJ
+            outx, outy = not 0 <= Ii < nc, not 0 <= Jj < nc
+            if not outx and not outy:
+                add((Ii, Jj), L - Kw * kc[Jj, Ii] ** 2)
+            elif outx and not outy:
+                edge_ghost((clamp(Ii), Jj), (inward(Ii), Jj), L)
+            elif outy and not outx:
+                edge_ghost((Ii, clamp(Jj)), (Ii, inward(Jj)), L)
+            else:
+                # the corner ghost's neighbours: beyond (clamp(Ii), Jj) in y and
+                # beyond (Ii, clamp(Jj)) in x
+                edge_ghost((clamp(Ii), clamp(Jj)), (clamp(Ii), inward(Jj)), L / 2)
+                edge_ghost((clamp(Ii), clamp(Jj)), (inward(Ii), clamp(Jj)), L / 2)
+    if bc == 0:  # Dirichlet boundary nodes hold 0: their coefficients do not act
+        coef = {q: w for q, w in coef.items()
+                if 0 < q[0] < nc - 1 and 0 < q[1] < nc - 1}
+    return coef
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_redglk2_boundary_band_rows_with_variable_k(ora, bc):
+    """Rows of the ReD-Glk2 boundary band, probed column by column with unit
+    vectors and compared with the coefficients derived from the printed 5x5
+    stencils and the ghost rules (see _redglk2_expected_row), for a variable
+    wavenumber: a second-layer row at mid-edge on each side, second-layer rows
+    next to each corner (these reach the corner ghost), and the second-layer
+    corner node itself.  Taking the ghost's k at the inward node, or replacing
+    the corner average by one single-direction ghost, fails here."""
+    nc = 9
+    p, kc, H = _redglk2_probe_problem(ora, bc, nc)
+    A = _dense_coarse(ora, p, nc)
+    m = nc // 2
+    rows = [(1, m), (nc - 2, m), (m, 1), (m, nc - 2),          # mid-edge
+            (1, 2), (2, 1), (nc - 2, nc - 3), (nc - 3, nc - 2),  # next to a corner
+            (1, 1), (nc - 2, 1), (1, nc - 2), (nc - 2, nc - 2)]  # the corner ghost's row
+    scale = 980 / (256 * H * H)
+    for (I, J) in rows:
+        exp = _redglk2_expected_row(I, J, kc, H, nc, bc)
+        got = A[J * nc + I].reshape(nc, nc)
+        want = np.zeros((nc, nc), complex)
+        for (Ii, Jj), w in exp.items():
+            want[Jj, Ii] = w
+        if bc == 0:
+            got = _interior(got)
+        assert np.abs(got - want).max() <= 1e-12 * scale, (I, J)
+
+
+def test_redglk2_corner_row_by_hand(ora):
+    """One row written out by hand, Sommerfeld: the second-layer node (1, 1)
+    next to the corner.  Its 5x5 stencil reaches five ghosts at x = -1, five at
+    y = -1, and the corner ghost (-1, -1).  By eq. GhostPoint at spacing H with
+    k of the boundary node, and the corner rule of Section 5.2.5, the corner
+    ghost is (u_g(0,-1) + u_g(-1,0))/2 = u(0,1)/2 + u(1,0)/2 + 2iH k00 u(0,0).
+    Ghosts carry k = 0, so only their LAP weights enter.  The coefficient of
+    u(0,0) in this row is therefore
+      [LAP(-1,-1) + 2iH k00 (LAP(-2,-1) + LAP(-1,-2) + LAP(-2,-2))] / (256 H^2)
+      - K2(-1,-1) k00^2 / 4096
+    with LAP(-1,-1) = -112, LAP(-2,-1) = LAP(-1,-2) = -44, LAP(-2,-2) = -3 and
+    K2(-1,-1) = 784 (the printed stencils)."""
+    nc = 9
+    p, kc, H = _redglk2_probe_problem(ora, 1, nc)
+    e = np.zeros((nc, nc), complex)
+    e[0, 0] = 1
+    got = ora.coarse_apply(p, e)[1, 1]
+    k00 = kc[0, 0]
+    want = (-112 + 2j * H * k00 * (-44 - 44 - 3)) / (256 * H * H) - 784 * k00 ** 2 / 4096
+    assert abs(got - want) <= 1e-12 * abs(want)
+    # u(1, 0) (x = 1, y = 0): its own weight LAP(0,-1) = 56 minus its k^2 term
+    # (K2(0,-1) = 1960), the ghost (1, -1) beyond it (weight LAP(0,-2) = -98,
+    # k of (1, 0)), and half of the corner ghost (weight -3 / 2)
+    e = np.zeros((nc, nc), complex)
+    e[0, 1] = 1
+    got = ora.coarse_apply(p, e)[1, 1]
+    k10 = kc[0, 1]
+    # the ghost (-1, 0) beyond (0, 0) mirrors u(1, 0) with weight LAP(-2,-1) = -44
+    want = (56 + 2j * H * k10 * (-98) - 1.5 - 44) / (256 * H * H) - 1960 * k10 ** 2 / 4096
+    assert abs(got - want) <= 1e-12 * abs(want)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_redglk2_first_layer_rows_with_variable_k(ora, bc):
+    """First-layer rows keep the 5-point stencil of Section 2.1 at spacing H
+    (eqs. Sommerfeldstencil1/2) with the wavenumber of the row's own node:
+    edge rows get -2 i k H on the diagonal and -2 for the inward neighbour,
+    the corner row -4 i k H and two -2 couplings.  Dirichlet rows are held at 0."""
+    nc = 9
+    p, kc, H = _redglk2_probe_problem(ora, bc, nc)
+    A = _dense_coarse(ora, p, nc)
+    m = nc // 2
+
+    def row(I, J):
+        return A[J * nc + I].reshape(nc, nc) * H * H
+
+    if bc == 0:
+        for (I, J) in [(0, m), (m, 0), (0, 0), (nc - 1, nc - 1)]:
+            assert np.abs(row(I, J)).max() == 0
+        return
+    for (I, J, inw) in [(0, m, (1, m)), (nc - 1, m, (nc - 2, m)), (m, 0, (m, 1))]:
+        r = row(I, J)
+        k = kc[J, I]
+        want = np.zeros((nc, nc), complex)
+        want[J, I] = 4 - k * k * H * H - 2j * k * H
+        want[inw[1], inw[0]] = -2
+        tang = [(I, J - 1), (I, J + 1)] if I in (0, nc - 1) else [(I - 1, J), (I + 1, J)]
+        for (a, b) in tang:
+            want[b, a] = -1
+        assert np.abs(r - want).max() <= 1e-12, (I, J)
+    for (I, J) in [(0, 0), (nc - 1, 0), (0, nc - 1), (nc - 1, nc - 1)]:
+        r = row(I, J)
+        k = kc[J, I]
+        want = np.zeros((nc, nc), complex)
+        want[J, I] = 4 - k * k * H * H - 4j * k * H
+        want[J, 1 if I == 0 else nc - 2] = -2
+        want[1 if J == 0 else nc - 2, I] = -2
+        assert np.abs(r - want).max() <= 1e-12, (I, J)
+
+
 # --------------------------------------------------------------------------
 # CSLP V-cycle
 # --------------------------------------------------------------------------
@@ -546,8 +724,8 @@ def test_level_hierarchy(ora):
 
 
 # ---------------------------------------------------------------------------
-# Coarse-operator variants (Section 5.2.2, 5.2.4) and the GCR outer method
-# (Section 6.4)
+# Coarse-operator variants (Section 5.2.3, 5.2.4) and the GCR outer method
+# (Section 6.3)
 # ---------------------------------------------------------------------------
 def _poly_cases(X, Y):
     """(u, -Lap u) pairs of polynomials."""
@@ -602,7 +780,7 @@ def test_redo2_and_redo4_taylor(ora, bc):
 
 def test_redo4_printed_centre_reading(ora):
     """The centre weight of ReD-O4 is 60/(12 H^2) - k^2: the k^2 coefficient is
-    not divided by 12 as printed (reading of Section 5.2.2; the printed form
+    not divided by 12 as printed (reading of Section 5.2.3; the printed form
     would not be consistent with -Lap - k^2)."""
     n, k = 33, 7.0
     p = _prob(ora, n, k, 1, coarse_op=ora.COARSE_REDO4)
