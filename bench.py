@@ -10,11 +10,16 @@ the timed region.
 
 Prints ONE JSON line with the contract fields plus:
   roofline      the dominant kernel's algorithmic HBM bytes / its average
-                launch time (HIP events on the solver's stream, inside the
-                timed region), against the 8 TB/s HBM peak;
-  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload
-                (rank 0 only), extrapolated to solves/s with the GPU run's
-                iteration counts.
+                launch time, against the 8 TB/s HBM peak.  The solves are
+                timed twice: `value` from a region with no kernel timing, then
+                the same number of solves with HIP events recorded on the
+                solver's stream around each launch of that kernel (their
+                wall time is `ms_per_step_with_events`);
+  cpu_baseline  the CPU oracle (OpenMP build, all host threads; a one-thread
+                figure beside it) on the same workload: whole solves timed
+                on small grids; on large ones a bounded sample,
+                extrapolated to solves/s with the GPU run's iteration
+                counts.
 """
 import argparse
 import hashlib
@@ -51,11 +56,13 @@ def parse():
     ap.add_argument("--vc-tail", type=int, default=300000,
                     help="FP64 V-cycle: largest level (nodes) whose upward pass and those of "
                          "the levels below run fused in one launch (0 = one launch per level)")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
-                    help="mixed: complex64 fine-grid V-cycle and coarse-GMRES basis inside the "
-                         "FP64 solve")
-    ap.add_argument("--roofline-kernel", default="mdot",
-                    help="kernel class whose roofline is reported")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "mixed_c64basis"], default="fp64",
+                    help="mixed: complex64 fine-grid CSLP V-cycle and smoother inside the FP64 "
+                         "solve (coarse solve FP64); mixed_c64basis: also the coarse-GMRES "
+                         "basis in complex64")
+    ap.add_argument("--roofline-kernel", default="mupdate",
+                    help="kernel class whose roofline is reported (default: the Gram-Schmidt "
+                         "update, the kernel with the largest share of the solve's kernel time)")
     ap.add_argument("--roofline-level", type=int, default=1,
                     help="multigrid level of the timed kernel (-1 = any)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -87,52 +94,116 @@ def measured_traffic(kernel, workload):
     return e.get("bytes_per_launch")
 
 
+def host_cpu():
+    """The host CPU's model name and the threads this process may use."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
+
+
+def _oracle_problem(oracle, w, coarsest_nodes, **kw):
+    return oracle.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, k=w.kfield(), kconst=w.kconst,
+                          coarse_op=w.coarse_op, coarse_restart=w.coarse_restart,
+                          coarsest_nodes=coarsest_nodes, **kw)
+
+
+def cpu_baseline_full(w, coarsest_nodes, reps=5):
+    """Time whole oracle solves of the workload (small grids): the median of
+    `reps` solves with all host threads, and of 3 with one thread."""
+    import oracle
+    oracle.build(force=False)
+    P = _oracle_problem(oracle, w, coarsest_nodes, coarse_mode=oracle.CMODE_TOL,
+                        coarse_tol=w.coarse_tol, coarse_iters=w.coarse_maxit)
+    b = w.rhs()
+    model, nthr = host_cpu()
+    res = {}
+    for th, n in ((nthr, reps), (1, 3)):
+        oracle.set_threads(th)
+        ts = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            _, inf = oracle.fgmres(P, b, restart=w.restart, tol=w.tol, maxit=500)
+            ts.append(time.perf_counter() - t0)
+        res[th] = (sorted(ts)[len(ts) // 2], inf)
+    oracle.set_threads(nthr)
+    t, inf = res[nthr]
+    return {
+        "value": 1.0 / t, "unit": "solves/s", "cores": nthr, "kind": "oracle",
+        "sample": (f"whole oracle solves of the same workload ({w.nx}x{w.ny}): median of {reps} "
+                   f"with {nthr} threads {t:.3f} s, median of 3 with 1 thread "
+                   f"{res[1][0]:.3f} s; {inf.iters} outer / {inf.inner_total} inner iterations, "
+                   f"relres {inf.relres:.2e}; host {model}"),
+        "value_1thread": 1.0 / res[1][0],
+        "host": model,
+    }
+
+
 def cpu_baseline(w, info, coarsest_nodes):
     """Time the oracle on a bounded sample of the workload and extrapolate.
 
-    Sample (single-threaded C oracle, full 4097^2 grid): one A_h apply, one
-    coarse GMRES solve with 1 and with 8 fixed iterations (their difference
-    over 7 gives the cost of one inner iteration at the inner steps j = 1..7,
-    about the average step of a restart-15 cycle), and one A-DEF1 application with a
-    1-iteration coarse solve (the fine-grid part of an outer iteration).
-    Estimate of one solve = outer * (fine part + coarse-solve overhead + A_h)
-    + inner_total * (one inner iteration), with the GPU run's counts; the
-    outer Gram-Schmidt on the fine grid is left out (it favours the CPU)."""
+    Sample (C oracle, full grid, with all host threads and again with one):
+    one A_h apply, one coarse GMRES solve with 1 and with 8 fixed iterations
+    (their difference over 7 gives the cost of one inner iteration at the inner
+    steps j = 1..7, about the average step of a restart-15 cycle), and one
+    A-DEF1 application with a 1-iteration coarse solve (the fine-grid part of
+    an outer iteration).  Estimate of one solve = outer * (fine part +
+    coarse-solve overhead + A_h) + inner_total * (one inner iteration), with
+    the GPU run's counts; the outer Gram-Schmidt on the fine grid is left out
+    (it favours the CPU)."""
     import oracle
     from paper_2308_06152_amd import inputs
     oracle.build(force=False)
-    P = oracle.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, k=w.kfield(), kconst=w.kconst,
-                       coarse_op=w.coarse_op,
-                       coarse_mode=oracle.CMODE_FIXED, coarse_iters=1,
-                       coarse_restart=w.coarse_restart, coarsest_nodes=coarsest_nodes)
+    P = _oracle_problem(oracle, w, coarsest_nodes, coarse_mode=oracle.CMODE_FIXED,
+                        coarse_iters=1)
     nxc, nyc = oracle.coarse_dims(P)
     v = inputs.random_complex((w.ny, w.nx), 11)
     v1 = inputs.random_complex((nyc, nxc), 12)
-    t0 = time.perf_counter()
-    oracle.helm_apply(P, v)
-    t_a = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.coarse_solve(P, v1)
-    t_c1 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.coarse_solve(P.replace(coarse_iters=8), v1)
-    t_c8 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.deflate_apply(P, v, oracle.DEFL_ADEF1)
-    t_d1 = time.perf_counter() - t0
-    per_inner = max((t_c8 - t_c1) / 7.0, 0.0)
-    overhead = max(t_c1 - per_inner, 0.0)
-    fine = max(t_d1 - t_c1, 0.0)
-    est = info["outer_iters"] * (fine + overhead + t_a) + info["inner_iters_total"] * per_inner
-    sample_s = t_a + t_c1 + t_c8 + t_d1
+    model, nthr = host_cpu()
+
+    def sample():
+        t0 = time.perf_counter()
+        oracle.helm_apply(P, v)
+        t_a = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.coarse_solve(P, v1)
+        t_c1 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.coarse_solve(P.replace(coarse_iters=8), v1)
+        t_c8 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.deflate_apply(P, v, oracle.DEFL_ADEF1)
+        t_d1 = time.perf_counter() - t0
+        per_inner = max((t_c8 - t_c1) / 7.0, 0.0)
+        overhead = max(t_c1 - per_inner, 0.0)
+        fine = max(t_d1 - t_c1, 0.0)
+        est = (info["outer_iters"] * (fine + overhead + t_a)
+               + info["inner_iters_total"] * per_inner)
+        return est, (t_a, t_c1, t_c8, t_d1)
+
+    res = {}
+    for th in (nthr, 1):
+        oracle.set_threads(th)
+        res[th] = sample()
+    oracle.set_threads(nthr)
+    est, (t_a, t_c1, t_c8, t_d1) = res[nthr]
     return {
-        "value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
-        "sample": (f"single-threaded C oracle on the full {w.nx}x{w.ny} grid: A_h apply "
+        "value": 1.0 / est, "unit": "solves/s", "cores": nthr, "kind": "oracle",
+        "sample": (f"C oracle with {nthr} threads on the full {w.nx}x{w.ny} grid: A_h apply "
                    f"{t_a:.2f}s, coarse GMRES 1 it {t_c1:.2f}s / 8 it {t_c8:.2f}s, A-DEF1 with "
-                   f"1 inner it {t_d1:.2f}s (sample {sample_s:.1f}s); extrapolated to "
+                   f"1 inner it {t_d1:.2f}s (sample {sum(res[nthr][1]):.1f}s); extrapolated to "
                    f"{info['outer_iters']} outer + {info['inner_iters_total']} inner iterations "
-                   f"= {est:.0f}s per solve"),
+                   f"= {est:.0f}s per solve; the same sample with 1 thread "
+                   f"({sum(res[1][1]):.1f}s) gives {res[1][0]:.0f}s per solve; host {model}"),
         "est_seconds_per_solve": est,
+        "value_1thread": 1.0 / res[1][0],
+        "host": model,
     }
 
 
@@ -213,7 +284,8 @@ def main():
         w = {"large": inputs.large_plain, "small": inputs.small_plain,
              "wedge": inputs.wedge}[a.workload]()
     kf = w.kfield()
-    prec = H.PREC_MIXED if a.precision == "mixed" else H.PREC_FP64
+    prec = {"fp64": H.PREC_FP64, "mixed": H.PREC_MIXED,
+            "mixed_c64basis": H.PREC_MIXED_C64BASIS}[a.precision]
     S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc,
                  k=None if kf is None else torch.from_numpy(kf).cuda(), kconst=w.kconst,
                  coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
@@ -225,8 +297,7 @@ def main():
     torch.cuda.synchronize()
     for _ in range(a.warmup):
         S.solve(b, x)
-    kclass = H.KERNEL_CLASS_NAMES.index(a.roofline_kernel)
-    S.timing_enable(kclass, a.roofline_level)
+    # timed region: the solves alone (no kernel timing events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
@@ -235,15 +306,28 @@ def main():
         infos.append(info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    elapsed = t1 - t0
+    # second timed region, the same solves with HIP events recorded on the
+    # solver's stream around every launch of the roofline kernel
+    kclass = H.KERNEL_CLASS_NAMES.index(a.roofline_kernel)
+    S.timing_enable(kclass, a.roofline_level)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(a.steps):
+        S.solve(b, x)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     n_launch, k_ms, k_bytes = S.timing_read()
     S.timing_enable(-1, -1)
-    elapsed = t1 - t0
     last = infos[-1][0]
     if not all(i["converged"] for step in infos for i in step):
         print("bench.py: a solve did not converge", file=sys.stderr)
         sys.exit(1)
     achieved = (k_bytes / 1e9) / (k_ms / 1e3) if k_ms > 0 else 0.0
     traffic = measured_traffic(a.roofline_kernel, w.name) if prec == H.PREC_FP64 else None
+    mixed = prec != H.PREC_FP64
+    wname = w.name + {H.PREC_FP64: "", H.PREC_MIXED: "_mixed",
+                      H.PREC_MIXED_C64BASIS: "_mixed_c64basis"}[prec]
     line = {
         "metric": METRIC,
         "value": nrhs * a.steps / elapsed,
@@ -255,18 +339,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == H.PREC_FP64 else "f64 (f32 fine-grid V-cycle)",
+        "dtype": ("f64" if not mixed else "f64 (f32 fine-grid V-cycle"
+                  + (", c64 coarse basis)" if prec == H.PREC_MIXED_C64BASIS else ")")),
         "data": "synthetic",
         "config": {
-            "workload": w.name + ("_mixed" if prec == H.PREC_MIXED else ""),
+            "workload": wname,
             "grid": f"{w.nx}x{w.ny}",
             "k": w.kconst if kf is None else f"{w.model} model at {w.freq:g} Hz",
             "bc": "sommerfeld" if w.bc == H.BC_SOMMERFELD else "dirichlet",
             "source": "gaussian sigma=2h" if w.source == "gauss" else "point",
             "preconditioner": "APD (Bezier Z, " + ("ReD-Glk2" if w.coarse_op else "Galerkin")
                               + " A_2h) + 1 CSLP V-cycle (1,0.5)"
-                              + (" in complex64, complex64 coarse basis" if prec == H.PREC_MIXED
-                                 else ""),
+                              + ({H.PREC_FP64: "", H.PREC_MIXED: ", fine-grid V-cycle in complex64",
+                                  H.PREC_MIXED_C64BASIS: ", fine-grid V-cycle in complex64, "
+                                                         "complex64 coarse basis"}[prec]),
             "krylov": f"FGMRES({w.restart}) to {w.tol:g}",
             "coarse_solve": f"GMRES({w.coarse_restart}) to {w.coarse_tol:g}",
             "outer_iters": last["outer_iters"], "inner_iters_total": last["inner_iters_total"],
@@ -282,10 +368,32 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "launches": n_launch, "avg_launch_us": 1e3 * k_ms / max(n_launch, 1),
             "alg_bytes_per_launch": k_bytes / max(n_launch, 1),
+            "ms_per_step_with_events": 1e3 * (t3 - t2) / a.steps,
         },
     }
+    if mixed:
+        # accuracy of the mixed-precision solution: against the FP64 solve of
+        # the same workload (the FP64 path matches the oracle per solve)
+        S64 = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc,
+                       k=None if kf is None else torch.from_numpy(kf).cuda(), kconst=w.kconst,
+                       coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
+                       coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart,
+                       restart=w.restart, tol=w.tol, batch=a.batch, vc_tail=a.vc_tail)
+        x64, info64 = S64.solve(b)
+        S64.close()
+        xs, xr = x.reshape(nrhs, -1), x64.reshape(nrhs, -1)
+        diff = ((xs - xr).norm(dim=1) / xr.norm(dim=1)).max().item()
+        line["config"]["fp64_reference"] = {
+            "outer_iters": info64[0]["outer_iters"],
+            "inner_iters_total": info64[0]["inner_iters_total"],
+            "relres": info64[0]["relres"],
+            "max_rel_diff_to_fp64_solution": diff,
+        }
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, last, S.opts.coarsest_nodes)
+        if w.nx * w.ny <= 300 * 300:
+            line["cpu_baseline"] = cpu_baseline_full(w, S.opts.coarsest_nodes)
+        else:
+            line["cpu_baseline"] = cpu_baseline(w, last, S.opts.coarsest_nodes)
     print(json.dumps(line), flush=True)
 
 

@@ -69,7 +69,7 @@ enum {
  * `restart` steps; stops on the preconditioned residual relative to ||P b||). */
 enum { HELM_OUTER_FGMRES = 0, HELM_OUTER_GCR = 1, HELM_OUTER_GMRES_LEFT = 2 };
 enum { HELM_CMODE_FIXED = 1, HELM_CMODE_TOL = 2 };
-enum { HELM_PREC_FP64 = 0, HELM_PREC_MIXED = 1 };
+enum { HELM_PREC_FP64 = 0, HELM_PREC_MIXED = 1, HELM_PREC_MIXED_C64BASIS = 2 };
 
 /* The grid: nx x ny vertex nodes including the boundary, spacings hx, hy
  * (Section 2.1 takes hx = hy = h; ReD-Glk2 requires hx == hy). */
@@ -101,17 +101,21 @@ typedef struct {
                                 (default 1089 = 33 x 33; 0 = down to 3 x 3;
                                 at most 2048) */
     int precision;           /* HELM_PREC_FP64 (default): everything in FP64.
-                                HELM_PREC_MIXED: (1) the fine-grid CSLP V-cycle
-                                (cslp_vcycle, and M^{-1} inside A-DEF1) runs in
-                                complex64 on every level: it reads r in FP64,
-                                stores the levels in FP32 and writes z in FP64;
-                                (2) the coarse GMRES stores its Krylov basis in
-                                complex64 (when its V-cycle has a level below
-                                level 1), with A_2h, that V-cycle, the products
-                                and the updates in FP64.  The outer Krylov
-                                method, A_h, Z, Z^T and the residual test stay
-                                FP64; FGMRES absorbs the perturbed
-                                preconditioner (Section 5.2). */
+                                HELM_PREC_MIXED: the fine-grid CSLP V-cycle
+                                and its smoother (cslp_vcycle, and M^{-1}
+                                inside A-DEF1) run in complex64 on every
+                                level: the cycle reads r in FP64, stores the
+                                levels in FP32 and writes z in FP64.  The
+                                outer Krylov method, A_h, Z, Z^T, the
+                                deflation coarse solve (its basis, its V-cycle
+                                and A_2h) and the residual test stay FP64;
+                                FGMRES absorbs the perturbed preconditioner
+                                (Sections 3.1, 6.3).
+                                HELM_PREC_MIXED_C64BASIS: as HELM_PREC_MIXED,
+                                and the coarse GMRES also stores its Krylov
+                                basis in complex64 (when its V-cycle has a
+                                level below level 1), with A_2h, that V-cycle,
+                                the products and the updates in FP64. */
     int outer;               /* HELM_OUTER_* (default HELM_OUTER_FGMRES)       */
     int batch;               /* nrhs > 1 with the FP64 path: 1 (default) = all
                                 right-hand sides in one batched pass (one launch

@@ -10,6 +10,7 @@ which passage of the paper it follows and how it is pinned.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import dataclasses
 import os
@@ -28,13 +29,23 @@ DEFL_Q, DEFL_P, DEFL_ADEF1 = 0, 1, 2
 PRECOND_VCYCLE, PRECOND_EXACT_A = 0, 1
 
 
-def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so with gcc (plain -O2, no tuning)."""
-    if force or not os.path.exists(_SO):
-        cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
-               "-o", _SO, os.path.join(_HERE, "oracle.c"), "-lm"]
+_SO_SERIAL = os.path.join(_HERE, "liboracle_serial.so")
+# Plain optimisation for any x86-64 host with AVX2 and FMA (the build host and
+# the GPU host may differ, so no -march=native).  -fopenmp splits the
+# element-wise grid loops and the fixed-chunk sums over threads; the serial
+# build (same flags without -fopenmp) gives bit-identical results.
+_CFLAGS = ["-O3", "-march=x86-64-v3", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared"]
+
+
+def build(force: bool = True, serial: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (OpenMP) or liboracle_serial.so."""
+    so = _SO_SERIAL if serial else _SO
+    if force or not os.path.exists(so):
+        cmd = ["gcc", *_CFLAGS, *([] if serial else ["-fopenmp"]), "-o", so + ".tmp",
+               os.path.join(_HERE, "oracle.c"), "-lm"]
         subprocess.run(cmd, check=True)
-    return _SO
+        os.replace(so + ".tmp", so)
+    return so
 
 
 class _Problem(ctypes.Structure):
@@ -107,17 +118,38 @@ class Problem:
 
 
 _lib = None
+_libs = {}
+
+
+@contextlib.contextmanager
+def serial_build():
+    """Run the calls inside the block on the serial (no OpenMP) build."""
+    global _lib
+    saved = lib()
+    _lib = _load(_SO_SERIAL, serial=True)
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
-            build(force=False)
-        L = ctypes.CDLL(_SO)
+        _lib = _load(_SO, serial=False)
+    return _lib
+
+
+def _load(path: str, serial: bool) -> ctypes.CDLL:
+    if path not in _libs:
+        if not os.path.exists(path):
+            build(force=False, serial=serial)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER(_Problem)
         D = ctypes.POINTER(ctypes.c_double)
         IP = ctypes.POINTER(ctypes.c_int)
+        L.ora_set_threads.argtypes = [ctypes.c_int]
+        L.ora_set_threads.restype = None
         L.ora_num_levels.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.ora_level_dims.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, IP,
                                      IP]
@@ -136,8 +168,8 @@ def lib() -> ctypes.CDLL:
         L.ora_helm_apply_adjoint.argtypes = [P, D, D]
         L.ora_adjoint_solve.argtypes = [P, D, D]
         L.ora_grad_s.argtypes = [P, ctypes.c_double, D, D, D]
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 class OracleError(RuntimeError):
@@ -158,6 +190,15 @@ def _cin(a, shape) -> np.ndarray:
 def _check(rc: int, what: str):
     if rc != 0:
         raise OracleError(f"{what} failed with code {rc}")
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use (results do not depend on it)."""
+    return int(lib().ora_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().ora_set_threads(int(n))
 
 
 def num_levels(nx: int, ny: int, coarsest_nodes: int = 0) -> int:

@@ -27,6 +27,16 @@
 
 typedef double complex cplx;
 
+/* Loops whose iterations write disjoint outputs (one grid row, or one vector
+ * entry, each) may be split over OpenMP threads; the arithmetic of every
+ * output is the same either way. */
+#ifdef _OPENMP
+#include <omp.h>
+#define ORA_PARFOR _Pragma("omp parallel for schedule(static)")
+#else
+#define ORA_PARFOR
+#endif
+
 /* the imaginary unit; the single-letter macro of complex.h is released so that
  * I, J can name coarse-grid indices as in the paper */
 #define IU _Complex_I
@@ -62,6 +72,24 @@ typedef struct {
  * (0 = coarsen as far as possible).  The deflation coarse grid (level 1) is
  * always made. */
 static int coarsenable(int nx, int ny) { return nx >= 5 && ny >= 5 && (nx & 1) && (ny & 1); }
+
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 
 int ora_num_levels(int nx, int ny, int coarsest_nodes)
 {
@@ -203,6 +231,7 @@ static void stencil5(const lvl_t *g, cplx s, int i, int j, cplx c[5])
 /* y = (-Lap_h - s k^2) x  (the matrix-free matvec of Section 5.1). */
 static void op5(const lvl_t *g, cplx s, const cplx *x, cplx *y)
 {
+    ORA_PARFOR
     for (int j = 0; j < g->ny; j++)
         for (int i = 0; i < g->nx; i++) {
             size_t p = (size_t)j * g->nx + i;
@@ -254,6 +283,7 @@ typedef double (*w1d_t)(int);
  * non-unknown fine nodes are 0. */
 static void prolong(const lvl_t *gf, const lvl_t *gc, w1d_t w, const cplx *vc, cplx *vf)
 {
+    ORA_PARFOR
     for (int j = 0; j < gf->ny; j++)
         for (int i = 0; i < gf->nx; i++) {
             size_t p = (size_t)j * gf->nx + i;
@@ -283,6 +313,7 @@ static void prolong(const lvl_t *gf, const lvl_t *gc, w1d_t w, const cplx *vc, c
  * the linear weights it is 1/2 [1 2 1] per axis). */
 static void restrict_t(const lvl_t *gf, const lvl_t *gc, w1d_t w, const cplx *vf, cplx *vc)
 {
+    ORA_PARFOR
     for (int J = 0; J < gc->ny; J++)
         for (int I = 0; I < gc->nx; I++) {
             size_t P = (size_t)J * gc->nx + I;
@@ -313,6 +344,7 @@ static void restrict_t(const lvl_t *gf, const lvl_t *gc, w1d_t w, const cplx *vf
 static void fw_restrict(const lvl_t *gf, const lvl_t *gc, const cplx *vf, cplx *vc)
 {
     restrict_t(gf, gc, w_linear, vf, vc);
+    ORA_PARFOR
     for (size_t q = 0; q < npts(gc); q++) vc[q] *= 0.25;
 }
 
@@ -491,6 +523,7 @@ static int direct_solve_op(const lvl_t *g, int rx, int ry, gridop_t op, const vo
 static void jacobi(const lvl_t *g, cplx s, double omega, const cplx *r, cplx *x, cplx *t)
 {
     op5(g, s, x, t);
+    ORA_PARFOR
     for (int j = 0; j < g->ny; j++)
         for (int i = 0; i < g->nx; i++) {
             size_t p = (size_t)j * g->nx + i;
@@ -531,14 +564,17 @@ static int vcycle_rec(const hier_t *H, const ora_problem *p, int l, const cplx *
         free(pe);
         return ORA_ENOMEM;
     }
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) x[q] = 0;
     for (int it = 0; it < p->nu_pre; it++) jacobi(g, s, p->omega, r, x, t);
     op5(g, s, x, t);
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) t[q] = r[q] - t[q];
     fw_restrict(g, gc, t, rc);
     int rcode = vcycle_rec(H, p, l + 1, rc, ec);
     if (!rcode) {
         prolong(g, gc, w_linear, ec, pe);
+        ORA_PARFOR
         for (size_t q = 0; q < n; q++) x[q] += pe[q];
         for (int it = 0; it < p->nu_post; it++) jacobi(g, s, p->omega, r, x, t);
     }
@@ -587,6 +623,7 @@ static void coarse_galerkin(const hier_t *H, const ora_problem *p, const cplx *x
     cplx *a = (cplx *)malloc(npts(gf) * sizeof(cplx));
     cplx *b = (cplx *)malloc(npts(gf) * sizeof(cplx));
     if (!a || !b) { /* out of memory: poison the result */
+        ORA_PARFOR
         for (size_t q = 0; q < npts(gc); q++) y[q] = NAN;
         free(a);
         free(b);
@@ -648,6 +685,7 @@ static void coarse_redglk2(const hier_t *H, const cplx *u, cplx *y)
 {
     const lvl_t *g = &H->L[1];
     const double H2 = g->hx * g->hx; /* (2h)^2, hx == hy checked by the caller */
+    ORA_PARFOR
     for (int J = 0; J < g->ny; J++)
         for (int I0 = 0; I0 < g->nx; I0++) {
             size_t P = (size_t)J * g->nx + I0;
@@ -708,6 +746,7 @@ static cplx uval(const lvl_t *g, const cplx *u, int I, int J)
 static void coarse_redo2(const hier_t *H, const cplx *u, cplx *y)
 {
     const lvl_t *g = &H->L[1];
+    ORA_PARFOR
     for (int J = 0; J < g->ny; J++)
         for (int I = 0; I < g->nx; I++)
             y[(size_t)J * g->nx + I] = is_unknown(g, I, J) ? row_o2(g, u, I, J) : 0;
@@ -723,6 +762,7 @@ static void coarse_redo4(const hier_t *H, const cplx *u, cplx *y)
 {
     const lvl_t *g = &H->L[1];
     const double ax = 1.0 / (12.0 * g->hx * g->hx), ay = 1.0 / (12.0 * g->hy * g->hy);
+    ORA_PARFOR
     for (int J = 0; J < g->ny; J++)
         for (int I = 0; I < g->nx; I++) {
             size_t P = (size_t)J * g->nx + I;
@@ -750,6 +790,7 @@ static void coarse_redglk1(const hier_t *H, const cplx *u, cplx *y)
 {
     const lvl_t *g = &H->L[1];
     const double H2 = g->hx * g->hx; /* hx == hy checked by the caller */
+    ORA_PARFOR
     for (int J = 0; J < g->ny; J++)
         for (int I = 0; I < g->nx; I++) {
             size_t P = (size_t)J * g->nx + I;
@@ -796,17 +837,38 @@ static void coarse_cb(const void *ctx, const cplx *x, cplx *y)
 /* Krylov helpers                                                            */
 /* ------------------------------------------------------------------------- */
 
+/* Sums over a vector are taken over ORA_NCHUNK fixed contiguous chunks, each
+ * summed in index order, then the chunk sums in chunk order: the same
+ * rounding whether or not the chunks are summed by several threads. */
+#define ORA_NCHUNK 64
+
 static cplx dotc(size_t n, const cplx *a, const cplx *b) /* (a, b) = b^H a */
 {
+    cplx part[ORA_NCHUNK];
+    ORA_PARFOR
+    for (int c = 0; c < ORA_NCHUNK; c++) {
+        const size_t q0 = n * c / ORA_NCHUNK, q1 = n * (c + 1) / ORA_NCHUNK;
+        cplx s = 0;
+        for (size_t q = q0; q < q1; q++) s += conj(b[q]) * a[q];
+        part[c] = s;
+    }
     cplx s = 0;
-    for (size_t q = 0; q < n; q++) s += conj(b[q]) * a[q];
+    for (int c = 0; c < ORA_NCHUNK; c++) s += part[c];
     return s;
 }
 
 static double nrm2(size_t n, const cplx *a)
 {
+    double part[ORA_NCHUNK];
+    ORA_PARFOR
+    for (int c = 0; c < ORA_NCHUNK; c++) {
+        const size_t q0 = n * c / ORA_NCHUNK, q1 = n * (c + 1) / ORA_NCHUNK;
+        double s = 0;
+        for (size_t q = q0; q < q1; q++) s += creal(a[q]) * creal(a[q]) + cimag(a[q]) * cimag(a[q]);
+        part[c] = s;
+    }
     double s = 0;
-    for (size_t q = 0; q < n; q++) s += creal(a[q]) * creal(a[q]) + cimag(a[q]) * cimag(a[q]);
+    for (int c = 0; c < ORA_NCHUNK; c++) s += part[c];
     return sqrt(s);
 }
 
@@ -865,15 +927,18 @@ static int gmres_right(size_t n, vop_t A, void *actx, vop_t Minv, void *mctx, co
     }
     const int cap = fixed > 0 ? fixed : maxit;
     const double bnorm = nrm2(n, b);
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) x[q] = 0;
     if (bnorm == 0) goto done;
     for (;;) {
         /* r = b - A x */
         if ((rc = A(actx, x, w))) goto done;
+        ORA_PARFOR
         for (size_t q = 0; q < n; q++) w[q] = b[q] - w[q];
         double beta = nrm2(n, w);
         if (fixed <= 0 && beta <= tol * bnorm) break;
         if (it >= cap || beta == 0) break;
+        ORA_PARFOR
         for (size_t q = 0; q < n; q++) V[q] = w[q] / beta;
         memset(g, 0, (size_t)(m + 1) * sizeof(cplx));
         g[0] = beta;
@@ -885,6 +950,7 @@ static int gmres_right(size_t n, vop_t A, void *actx, vop_t Minv, void *mctx, co
             for (int i = 0; i <= j; i++) {
                 cplx h = dotc(n, w, V + (size_t)i * n);
                 Hm[i * ldh + j] = h;
+                ORA_PARFOR
                 for (size_t q = 0; q < n; q++) w[q] -= h * V[(size_t)i * n + q];
             }
             double hn = nrm2(n, w);
@@ -900,6 +966,7 @@ static int gmres_right(size_t n, vop_t A, void *actx, vop_t Minv, void *mctx, co
             it++;
             jend = j + 1;
             if (hn != 0)
+                ORA_PARFOR
                 for (size_t q = 0; q < n; q++) vn[q] = w[q] / hn;
             if (fixed <= 0 && cabs(g[j + 1]) <= tol * bnorm) {
                 stop = 1;
@@ -911,10 +978,14 @@ static int gmres_right(size_t n, vop_t A, void *actx, vop_t Minv, void *mctx, co
             }
         }
         backsub(jend, ldh, Hm, g, y);
+        ORA_PARFOR
         for (size_t q = 0; q < n; q++) w[q] = 0;
-        for (int i = 0; i < jend; i++)
+        for (int i = 0; i < jend; i++) {
+            ORA_PARFOR
             for (size_t q = 0; q < n; q++) w[q] += y[i] * V[(size_t)i * n + q];
+        }
         if ((rc = Minv(mctx, w, z))) goto done;
+        ORA_PARFOR
         for (size_t q = 0; q < n; q++) x[q] += z[q];
         if (it >= cap) break;
         if (stop && fixed > 0) break; /* breakdown in fixed mode */
@@ -1023,7 +1094,9 @@ static int deflate_h(const hier_t *H, const ora_problem *p, int mode, const cplx
         goto done;
     }
     op5(gf, 1.0, vp, t);
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) t[q] = v[q] - t[q];
+    ORA_PARFOR
     for (int j = 0; j < gf->ny; j++) /* v itself carries no boundary value */
         for (int i = 0; i < gf->nx; i++)
             if (!is_unknown(gf, i, j)) t[(size_t)j * gf->nx + i] = 0;
@@ -1032,6 +1105,7 @@ static int deflate_h(const hier_t *H, const ora_problem *p, int mode, const cplx
         goto done;
     }
     if ((rc = precond_h(H, p, t, w))) goto done;
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) w[q] += vp[q];
 done:
     free(v1);
@@ -1169,6 +1243,7 @@ int ora_direct_solve(const ora_problem *p, const double *b, double *x)
 static void op5_adj(const lvl_t *g, const cplx *x, cplx *y)
 {
     const size_t n = npts(g);
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) y[q] = 0;
     for (int j = 0; j < g->ny; j++)
         for (int i = 0; i < g->nx; i++) {
@@ -1223,6 +1298,7 @@ int ora_grad_s(const ora_problem *p, double omega, const double *uin, const doub
     if (rc) return rc;
     const lvl_t *L = &H.L[0];
     const cplx *u = (const cplx *)uin, *lam = (const cplx *)lin;
+    ORA_PARFOR
     for (int j = 0; j < L->ny; j++)
         for (int i = 0; i < L->nx; i++) {
             size_t q = (size_t)j * L->nx + i;
@@ -1245,6 +1321,7 @@ int ora_grad_s(const ora_problem *p, double omega, const double *uin, const doub
 /* Zero the non-unknown (Dirichlet boundary) entries of a fine vector. */
 static void mask_unknowns(const lvl_t *g, cplx *v)
 {
+    ORA_PARFOR
     for (int j = 0; j < g->ny; j++)
         for (int i = 0; i < g->nx; i++)
             if (!is_unknown(g, i, j)) v[(size_t)j * g->nx + i] = 0;
@@ -1287,6 +1364,7 @@ int ora_fgmres(const ora_problem *p, const double *bin, double *xout, int m, dou
     }
     memcpy(b, bin, n * sizeof(cplx));
     mask_unknowns(g, b);
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) x[q] = 0;
     const double bnorm = nrm2(n, b);
     const int cap = force_iters > 0 ? force_iters : maxit;
@@ -1296,6 +1374,7 @@ int ora_fgmres(const ora_problem *p, const double *bin, double *xout, int m, dou
     }
     for (;;) {
         op5(g, 1.0, x, w);
+        ORA_PARFOR
         for (size_t q = 0; q < n; q++) w[q] = b[q] - w[q];
         double beta = nrm2(n, w);
         inf.relres = beta / bnorm;
@@ -1304,6 +1383,7 @@ int ora_fgmres(const ora_problem *p, const double *bin, double *xout, int m, dou
             break;
         }
         if (inf.iters >= cap || beta == 0) break;
+        ORA_PARFOR
         for (size_t q = 0; q < n; q++) V[q] = w[q] / beta;
         memset(gv, 0, (size_t)(m + 1) * sizeof(cplx));
         gv[0] = beta;
@@ -1324,6 +1404,7 @@ int ora_fgmres(const ora_problem *p, const double *bin, double *xout, int m, dou
             for (int i = 0; i <= j; i++) {
                 cplx h = dotc(n, w, V + (size_t)i * n);
                 Hm[i * ldh + j] = h;
+                ORA_PARFOR
                 for (size_t q = 0; q < n; q++) w[q] -= h * V[(size_t)i * n + q];
             }
             double hn = nrm2(n, w);
@@ -1339,15 +1420,19 @@ int ora_fgmres(const ora_problem *p, const double *bin, double *xout, int m, dou
             inf.iters++;
             jend = j + 1;
             if (hn != 0)
+                ORA_PARFOR
                 for (size_t q = 0; q < n; q++) vn[q] = w[q] / hn;
             if (force_iters <= 0 && cabs(gv[j + 1]) <= tol * bnorm) break;
             if (hn == 0) break;
         }
         backsub(jend, ldh, Hm, gv, y);
-        for (int i = 0; i < jend; i++)
+        for (int i = 0; i < jend; i++) {
+            ORA_PARFOR
             for (size_t q = 0; q < n; q++) x[q] += y[i] * Zs[(size_t)i * n + q];
+        }
         if (force_iters > 0 && inf.iters >= cap) {
             op5(g, 1.0, x, w);
+            ORA_PARFOR
             for (size_t q = 0; q < n; q++) w[q] = b[q] - w[q];
             inf.relres = nrm2(n, w) / bnorm;
             inf.converged = inf.relres <= tol;
@@ -1404,6 +1489,7 @@ int ora_gcr(const ora_problem *p, const double *bin, double *xout, int m, double
     }
     memcpy(b, bin, n * sizeof(cplx));
     mask_unknowns(g, b);
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) x[q] = 0;
     const double bnorm = nrm2(n, b);
     const int cap = force_iters > 0 ? force_iters : maxit;
@@ -1414,6 +1500,7 @@ int ora_gcr(const ora_problem *p, const double *bin, double *xout, int m, double
     for (;;) {
         /* (re)start from the true residual */
         op5(g, 1.0, x, r);
+        ORA_PARFOR
         for (size_t q = 0; q < n; q++) r[q] = b[q] - r[q];
         inf.relres = nrm2(n, r) / bnorm;
         if (force_iters <= 0 && inf.relres <= tol) {
@@ -1437,6 +1524,7 @@ int ora_gcr(const ora_problem *p, const double *bin, double *xout, int m, double
             for (int i = 0; i < j; i++) {
                 const cplx *wi = Ws + (size_t)i * n, *zi = Zs + (size_t)i * n;
                 cplx beta = dotc(n, wj, wi);
+                ORA_PARFOR
                 for (size_t q = 0; q < n; q++) {
                     wj[q] -= beta * wi[q];
                     zj[q] -= beta * zi[q];
@@ -1445,11 +1533,13 @@ int ora_gcr(const ora_problem *p, const double *bin, double *xout, int m, double
             double nu = nrm2(n, wj);
             inf.iters++;
             if (nu == 0) break; /* breakdown: A P r lies in the span already searched */
+            ORA_PARFOR
             for (size_t q = 0; q < n; q++) {
                 wj[q] /= nu;
                 zj[q] /= nu;
             }
             cplx alpha = dotc(n, r, wj);
+            ORA_PARFOR
             for (size_t q = 0; q < n; q++) {
                 x[q] += alpha * zj[q];
                 r[q] -= alpha * wj[q];
@@ -1458,6 +1548,7 @@ int ora_gcr(const ora_problem *p, const double *bin, double *xout, int m, double
         }
         if (force_iters > 0 && inf.iters >= cap) {
             op5(g, 1.0, x, r);
+            ORA_PARFOR
             for (size_t q = 0; q < n; q++) r[q] = b[q] - r[q];
             inf.relres = nrm2(n, r) / bnorm;
             inf.converged = inf.relres <= tol;
@@ -1513,6 +1604,7 @@ int ora_gmres_left(const ora_problem *p, const double *bin, double *xout, double
     }
     memcpy(b, bin, n * sizeof(cplx));
     mask_unknowns(g, b);
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) x[q] = 0;
     /* r0 = P (b - A u0) with u0 = 0 */
     if ((rc = deflate_h(&H, p, ORA_DEFL_ADEF1, b, w, &inner))) goto done;
@@ -1523,6 +1615,7 @@ int ora_gmres_left(const ora_problem *p, const double *bin, double *xout, double
         inf.converged = 1;
         goto done;
     }
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) V[q] = w[q] / beta;
     gv[0] = beta;
     int jend = 0;
@@ -1535,6 +1628,7 @@ int ora_gmres_left(const ora_problem *p, const double *bin, double *xout, double
         for (int i = 0; i <= j; i++) {
             cplx h = dotc(n, w, V + (size_t)i * n);
             Hm[i * ldh + j] = h;
+            ORA_PARFOR
             for (size_t q = 0; q < n; q++) w[q] -= h * V[(size_t)i * n + q];
         }
         double hn = nrm2(n, w);
@@ -1550,6 +1644,7 @@ int ora_gmres_left(const ora_problem *p, const double *bin, double *xout, double
         inf.iters++;
         jend = j + 1;
         if (hn != 0)
+            ORA_PARFOR
             for (size_t q = 0; q < n; q++) vn[q] = w[q] / hn;
         if (cabs(gv[j + 1]) <= tol * beta) {
             inf.converged = 1;
@@ -1558,9 +1653,12 @@ int ora_gmres_left(const ora_problem *p, const double *bin, double *xout, double
         if (hn == 0) break;
     }
     backsub(jend, ldh, Hm, gv, y);
-    for (int i = 0; i < jend; i++)
+    for (int i = 0; i < jend; i++) {
+        ORA_PARFOR
         for (size_t q = 0; q < n; q++) x[q] += y[i] * V[(size_t)i * n + q];
+    }
     op5(g, 1.0, x, w);
+    ORA_PARFOR
     for (size_t q = 0; q < n; q++) w[q] = b[q] - w[q];
     inf.relres = nrm2(n, w) / nrm2(n, b);
 done:

@@ -82,6 +82,11 @@ typedef struct {
 } ora_info;
 
 /* Level hierarchy of the V-cycle: number of levels and the dims of level l. */
+/* Threads the element-wise loops and chunked sums use (1 in the serial
+ * build); results do not depend on it. */
+int ora_threads(void);
+void ora_set_threads(int n);
+
 int ora_num_levels(int nx, int ny, int coarsest_nodes);
 int ora_level_dims(int nx, int ny, int coarsest_nodes, int l, int *lnx, int *lny);
 

@@ -24,6 +24,7 @@
 using namespace hd;
 typedef std::complex<double> zc;
 
+
 namespace {
 
 constexpr int MAXLEV = 40;
@@ -505,7 +506,7 @@ int vcycle(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2
            const cd *rs = nullptr)
 {
     const int Lc = h->nlev - 1;
-    if (l0 == 0 && h->o.precision == HELM_PREC_MIXED && !rs)
+    if (l0 == 0 && h->o.precision != HELM_PREC_FP64 && !rs)
         return vcycle_mixed(h, r, z, accumulate, v2);
     if (l0 == Lc) {
         // the cycle is the exact coarsest solve; it is linear, so a right-hand
@@ -1706,7 +1707,7 @@ int setup_coarsest(helm_ctx *h, const std::vector<std::vector<double>> &khost)
         }
     RCHK(dalloc(&h->cinv, (size_t)n * n));
     HCHK(hipMemcpy(h->cinv, inv.data(), inv.size() * sizeof(cd), hipMemcpyHostToDevice));
-    if (h->o.precision == HELM_PREC_MIXED) {
+    if (h->o.precision != HELM_PREC_FP64) {
         std::vector<cf> invf(inv.size());
         for (size_t q = 0; q < inv.size(); q++)
             invf[q] = make_float2((float)inv[q].x, (float)inv[q].y);
@@ -1797,7 +1798,9 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (o.restart < 1 || o.restart > MAX_RESTART || o.maxit < 1) return HELM_EINVAL;
     if (!(o.tol >= 0) || !(o.coarse_tol >= 0)) return HELM_EINVAL;
     if (o.coarsest_nodes < 0 || o.coarsest_nodes > MAX_COARSEST) return HELM_EINVAL;
-    if (o.precision != HELM_PREC_FP64 && o.precision != HELM_PREC_MIXED) return HELM_EINVAL;
+    if (o.precision != HELM_PREC_FP64 && o.precision != HELM_PREC_MIXED &&
+        o.precision != HELM_PREC_MIXED_C64BASIS)
+        return HELM_EINVAL;
     if (!k_dev && (!std::isfinite(k_const) || k_const < 0)) return HELM_ENONFINITE;
 
     helm_ctx *h = new (std::nothrow) helm_ctx();
@@ -1859,8 +1862,8 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     for (int l = 1; l < h->nlev && !rc; l++) {
         rc = dalloc(&h->L[l].r, h->L[l].n());
         if (!rc) rc = dalloc(&h->L[l].x, h->L[l].n());
-        if (!rc && o.precision == HELM_PREC_MIXED) rc = dalloc(&h->L[l].rf, h->L[l].n());
-        if (!rc && o.precision == HELM_PREC_MIXED) rc = dalloc(&h->L[l].xf, h->L[l].n());
+        if (!rc && o.precision != HELM_PREC_FP64) rc = dalloc(&h->L[l].rf, h->L[l].n());
+        if (!rc && o.precision != HELM_PREC_FP64) rc = dalloc(&h->L[l].xf, h->L[l].n());
     }
     if (!rc) rc = setup_coarsest(h, kh);
     // deflation and inner-GMRES workspace
@@ -1873,9 +1876,9 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (!rc) rc = dalloc(&h->wc, nc);
     if (!rc) rc = dalloc(&h->zc_, nc);
     if (!rc) rc = dalloc(&h->xin, nc);
-    // with the mixed-precision option the inner basis is complex64 (when the
+    // with HELM_PREC_MIXED_C64BASIS the inner basis is complex64 (when the
     // inner V-cycle has a level below level 1)
-    h->basis32 = o.precision == HELM_PREC_MIXED && h->nlev > 2;
+    h->basis32 = o.precision == HELM_PREC_MIXED_C64BASIS && h->nlev > 2;
     if (!rc && h->basis32) rc = dalloc(&h->Vc32, (size_t)(h->mc + 1) * nc);
     if (!rc && h->basis32) rc = dalloc(&h->wtmp, nc);
     h->part_blocks = krylov_blocks_max(nf);

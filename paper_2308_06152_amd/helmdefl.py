@@ -22,7 +22,7 @@ DEFL_Q, DEFL_P, DEFL_ADEF1 = 0, 1, 2
 Z_LINEAR, Z_HIGH = 0, 1
 COARSE_GALERKIN, COARSE_REDGLK2, COARSE_REDO2, COARSE_REDO4, COARSE_REDGLK1 = 0, 1, 2, 3, 4
 CMODE_FIXED, CMODE_TOL = 1, 2
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_MIXED_C64BASIS = 0, 1, 2
 OUTER_FGMRES, OUTER_GCR, OUTER_GMRES_LEFT = 0, 1, 2
 K_APPLY, K_VC_DOWN, K_VC_UP, K_ZT, K_DRESID, K_COARSE, K_DOT, K_UPDATE = range(8)
 KERNEL_CLASS_NAMES = ["apply5", "vc_down", "vc_up", "zt", "dresid", "coarse_op", "mdot",

@@ -76,7 +76,7 @@ def test_create_rejects_uncoarsenable_grids(H, nx, ny):
                                 dict(restart=61), dict(coarse_restart=0), dict(coarse_iters=0),
                                 dict(coarse_mode=0), dict(coarse_op=7), dict(defl_vectors=3),
                                 dict(omega=0.0), dict(tol=-1.0), dict(coarsest_nodes=-1),
-                                dict(coarsest_nodes=5000), dict(precision=2),
+                                dict(coarsest_nodes=5000), dict(precision=3),
                                 dict(precision=-1), dict(coarse_op=5), dict(coarse_op=-1),
                                 dict(outer=3), dict(outer=-1), dict(batch=2),
                                 dict(graphs=2), dict(graphs=-1), dict(vc_tail=-1)])

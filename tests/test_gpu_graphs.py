@@ -39,7 +39,7 @@ def test_graph_coarse_solve_replays_match_direct(H, ora, case):
         torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_graph_solve_matches_direct(H, ora, precision):
     case = ("som129", 129, 129, 1, "const", 30.0, 1)
     kw = dict(coarse_mode=2, coarse_tol=0.1, coarse_iters=300, coarse_restart=15,

@@ -64,7 +64,7 @@ def test_vcycle_fused_tail_level_limits(H, ora, limit):
     assert np.array_equal(host(Sf.vcycle(dev(r))), host(Sl.vcycle(dev(r))))
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 @pytest.mark.parametrize("case,coarsest", TCASES[:2] + TCASES[3:4], ids=["dir129", "som257",
                                                                           "som161_vark"])
 def test_coarse_solve_fused_tail_matches_per_level(H, ora, case, coarsest, precision):
