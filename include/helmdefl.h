@@ -45,7 +45,8 @@ typedef enum {
     HELM_ENONFINITE = -3, /* NaN or Inf in k or in a right-hand side              */
     HELM_ENOMEM = -4,     /* device or host allocation failed                    */
     HELM_EHIP = -5,       /* a HIP runtime call or kernel launch failed          */
-    HELM_ENOCONV = -6     /* solver stopped at maxit above the tolerance         */
+    HELM_ENOCONV = -6,    /* solver stopped at maxit above the tolerance         */
+    HELM_ESCRATCH = -7    /* cslp_vcycle_noalloc: levels exceed its fixed scratch */
 } helm_status;
 
 enum { HELM_BC_DIRICHLET = 0, HELM_BC_SOMMERFELD = 1 };
@@ -193,6 +194,21 @@ int helm_apply(helm_ctx *h, const void *x, void *y, int nrhs);
  * With opts.precision == HELM_PREC_MIXED the cycle computes in complex64
  * (r and z stay complex128 in memory). */
 int cslp_vcycle(helm_ctx *h, const void *r, void *z, int nrhs);
+
+/* cslp_vcycle (one right-hand side after another) for callers that cannot
+ * allocate device memory, e.g. code under HIP graph capture or a serving loop
+ * that forbids hipMalloc.  The V-cycle's level buffers (levels >= 1) live in a
+ * fixed device array of 64 MiB per GPU, held until the process ends, instead
+ * of the handle's buffers; the call allocates nothing and creates no events
+ * (kernel timing is suspended inside it).  The levels take 2 n_l complex128
+ * values each (complex64 with a mixed-precision handle), rounded up to 256
+ * bytes, about 10.7 bytes per fine-grid node in FP64: a 2049 x 2049 grid takes
+ * 45 MB; 4097 x 4097 does not fit.  HELM_ESCRATCH, before anything is
+ * launched, if they do not fit.
+ * Every call on one GPU shares that array: calls that may overlap in time on
+ * one GPU (different streams, or different host threads) race and must be
+ * serialised by the caller.  Arguments and results as for cslp_vcycle. */
+int cslp_vcycle_noalloc(helm_ctx *h, const void *r, void *z, int nrhs);
 
 /* Deflation applied to v (Sections 3.2.2 and 5.2): with v1 = Z^T v,
  * v2 ~= A_2h^{-1} v1 (per coarse_mode), v' = Z v2:

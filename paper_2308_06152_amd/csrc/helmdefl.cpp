@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -24,6 +25,36 @@
 using namespace hd;
 typedef std::complex<double> zc;
 
+// Fixed device scratch of cslp_vcycle_noalloc: the level buffers (r and x on
+// levels >= 1, FP64 or complex64) of such a call live here instead of in the
+// handle.  Every GPU that loads the library holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in: kernels
+// are given the device address that hipGetSymbolAddress returns for it, kept
+// per device in g_scratch_dev.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) double2 scratch[NOALLOC_SCRATCH_BYTES / sizeof(double2)];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device `dev` (the current device), looked up
+// once per device.
+int scratch_init(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return HELM_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[dev]) return HELM_OK;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return HELM_EHIP;
+    }
+    g_scratch_dev[dev] = p;
+    return HELM_OK;
+}
+}  // namespace
 
 namespace {
 
@@ -134,6 +165,7 @@ struct helm_ctx {
     helm_grid g{};
     helm_opts o{};
     hipStream_t st = nullptr;
+    int dev = 0;  // the HIP device current at helm_create
     double kconst = 0;
     int nlev = 0;
     LevelH L[MAXLEV];
@@ -1803,8 +1835,12 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
         return HELM_EINVAL;
     if (!k_dev && (!std::isfinite(k_const) || k_const < 0)) return HELM_ENONFINITE;
 
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HELM_EHIP;
+    RCHK(scratch_init(dev));
     helm_ctx *h = new (std::nothrow) helm_ctx();
     if (!h) return HELM_ENOMEM;
+    h->dev = dev;
     h->g = *g;
     h->o = o;
     h->st = (hipStream_t)stream;
@@ -1923,6 +1959,56 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
 
 bool valid(helm_ctx *h) { return h != nullptr; }
 
+// The handle's V-cycle level buffers pointed into the fixed scratch for the
+// length of one call (restored, with kernel timing, on scope exit).
+struct ScratchLevels {
+    helm_ctx *h;
+    cd *r[MAXLEV] = {}, *x[MAXLEV] = {};
+    cf *rf[MAXLEV] = {}, *xf[MAXLEV] = {};
+    int t_cls;
+    explicit ScratchLevels(helm_ctx *h_) : h(h_), t_cls(h_->t_cls)
+    {
+        for (int l = 0; l < h->nlev; l++) {
+            r[l] = h->L[l].r;
+            x[l] = h->L[l].x;
+            rf[l] = h->L[l].rf;
+            xf[l] = h->L[l].xf;
+        }
+    }
+    // Lay levels 1..nlev-1 out in `base` (16-node aligned); false if they do
+    // not fit in NOALLOC_SCRATCH_BYTES.
+    bool place(char *base)
+    {
+        const bool fp32 = h->o.precision != HELM_PREC_FP64;
+        const size_t node = fp32 ? sizeof(cf) : sizeof(cd);
+        size_t off = 0;
+        for (int l = 1; l < h->nlev; l++) {
+            const size_t b = ((h->L[l].n() * node + 255) / 256) * 256;
+            if (off + 2 * b > NOALLOC_SCRATCH_BYTES) return false;
+            if (fp32) {
+                h->L[l].rf = (cf *)(base + off);
+                h->L[l].xf = (cf *)(base + off + b);
+            } else {
+                h->L[l].r = (cd *)(base + off);
+                h->L[l].x = (cd *)(base + off + b);
+            }
+            off += 2 * b;
+        }
+        h->t_cls = -1;  // no timing events are created inside the call
+        return true;
+    }
+    ~ScratchLevels()
+    {
+        for (int l = 0; l < h->nlev; l++) {
+            h->L[l].r = r[l];
+            h->L[l].x = x[l];
+            h->L[l].rf = rf[l];
+            h->L[l].xf = xf[l];
+        }
+        h->t_cls = t_cls;
+    }
+};
+
 }  // namespace
 
 // ===========================================================================
@@ -2008,6 +2094,18 @@ int cslp_vcycle(helm_ctx *h, const void *r, void *z, int nrhs)
     } catch (...) {
         return HELM_ENOMEM;
     }
+    return HELM_OK;
+}
+
+int cslp_vcycle_noalloc(helm_ctx *h, const void *r, void *z, int nrhs)
+{
+    if (!valid(h) || !r || !z || nrhs < 1) return HELM_EINVAL;
+    if (h->dev < 0 || h->dev >= MAX_DEVICES || !g_scratch_dev[h->dev]) return HELM_EHIP;
+    ScratchLevels sl(h);
+    if (!sl.place((char *)g_scratch_dev[h->dev])) return HELM_ESCRATCH;
+    const size_t n = h->L[0].n();
+    for (int q = 0; q < nrhs; q++)
+        RCHK(vcycle(h, 0, (const cd *)r + q * n, (cd *)z + q * n, 0, nullptr));
     return HELM_OK;
 }
 
@@ -2124,6 +2222,8 @@ const char *helm_strerror(int code)
     case HELM_ENOMEM: return "out of memory";
     case HELM_EHIP: return "HIP runtime error";
     case HELM_ENOCONV: return "no convergence within maxit";
+    case HELM_ESCRATCH:
+        return "the V-cycle levels exceed the fixed 64 MiB scratch of cslp_vcycle_noalloc";
     default: return "unknown error";
     }
 }

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(HERE, "libhelmdefl.so")
 
 HELM_OK, HELM_EINVAL, HELM_EGRID, HELM_ENONFINITE = 0, -1, -2, -3
-HELM_ENOMEM, HELM_EHIP, HELM_ENOCONV = -4, -5, -6
+HELM_ENOMEM, HELM_EHIP, HELM_ENOCONV, HELM_ESCRATCH = -4, -5, -6, -7
 BC_DIRICHLET, BC_SOMMERFELD = 0, 1
 DEFL_Q, DEFL_P, DEFL_ADEF1 = 0, 1, 2
 Z_LINEAR, Z_HIGH = 0, 1
@@ -33,7 +33,7 @@ EXPORTED = [
     "helm_solve", "helm_destroy", "helm_strerror", "helm_coarse_dims", "helm_num_levels",
     "helm_level_dims", "helm_z_restrict", "helm_z_prolong", "helm_coarse_apply",
     "helm_coarse_solve", "helm_timing_enable", "helm_timing_read", "helm_adjoint_solve",
-    "helm_gradient_s", "helm_receivers",
+    "helm_gradient_s", "helm_receivers", "cslp_vcycle_noalloc",
 ]
 
 
@@ -82,6 +82,7 @@ def load() -> ctypes.CDLL:
                               vp, ctypes.POINTER(vp)]
     L.helm_apply.argtypes = [vp, vp, vp, cint]
     L.cslp_vcycle.argtypes = [vp, vp, vp, cint]
+    L.cslp_vcycle_noalloc.argtypes = [vp, vp, vp, cint]
     L.deflate_apply.argtypes = [vp, cint, vp, vp, cint]
     L.helm_solve.argtypes = [vp, vp, vp, cint, ctypes.POINTER(SolveInfo)]
     L.helm_destroy.argtypes = [vp]
@@ -205,6 +206,14 @@ class Solver:
         out = torch.empty_like(r) if out is None else out
         n = self._nrhs(r, (self.ny, self.nx))
         check(load().cslp_vcycle(self.h, _ptr(r), _ptr(out), n), "cslp_vcycle")
+        return out
+
+    def vcycle_noalloc(self, r, out):
+        """cslp_vcycle through the entry point that allocates nothing (the
+        level buffers live in the library's fixed device scratch); `out` must
+        be given."""
+        n = self._nrhs(r, (self.ny, self.nx))
+        check(load().cslp_vcycle_noalloc(self.h, _ptr(r), _ptr(out), n), "cslp_vcycle_noalloc")
         return out
 
     def deflate(self, v, mode: int = DEFL_ADEF1, out=None):

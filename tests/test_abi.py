@@ -55,6 +55,7 @@ def test_defaults_and_strerror(H):
     L = H.load()
     assert L.helm_strerror(0) == b"success"
     assert b"coarsen" in L.helm_strerror(H.HELM_EGRID)
+    assert b"scratch" in L.helm_strerror(H.HELM_ESCRATCH)
     assert L.helm_strerror(12345) == b"unknown error"
     assert L.helm_opts_default(None) == H.HELM_EINVAL
 
@@ -101,6 +102,7 @@ def test_null_arguments(H):
     assert L.helm_create(None, None, 1.0, None, None, ctypes.byref(h)) == H.HELM_EINVAL
     assert L.helm_apply(None, None, None, 1) == H.HELM_EINVAL
     assert L.cslp_vcycle(None, None, None, 1) == H.HELM_EINVAL
+    assert L.cslp_vcycle_noalloc(None, None, None, 1) == H.HELM_EINVAL
     assert L.deflate_apply(None, 2, None, None, 1) == H.HELM_EINVAL
     assert L.helm_solve(None, None, None, 1, None) == H.HELM_EINVAL
     assert L.helm_destroy(None) == H.HELM_EINVAL
