@@ -49,6 +49,10 @@ def parse():
                          "adjoint: misfit gradients on 1025 x 513 with 16 shots at 10 Hz")
     ap.add_argument("--nrhs", type=int, default=64, help="layered: sources solved together")
     ap.add_argument("--freq", type=float, default=10.0, help="layered: frequency in Hz")
+    ap.add_argument("--freqs", default="",
+                    help="layered: comma-separated frequencies (Hz); one step solves the "
+                         "--nrhs sources at each of them, one batched solve (and one handle) per "
+                         "frequency")
     ap.add_argument("--batch", type=int, choices=[0, 1], default=1,
                     help="layered: 1 = one batched solve of all sources, 0 = one after another")
     ap.add_argument("--graphs", type=int, choices=[0, 1], default=0,
@@ -65,6 +69,13 @@ def parse():
                          "update, the kernel with the largest share of the solve's kernel time)")
     ap.add_argument("--roofline-level", type=int, default=1,
                     help="multigrid level of the timed kernel (-1 = any)")
+    ap.add_argument("--autotune", choices=["off", "cache", "run"], default="cache",
+                    help="cache: take vc_tail / graphs / coarse restart from the autotuner's "
+                         "cache when it holds this workload on this device type (else the "
+                         "defaults); run: time the candidates first and record the choice; "
+                         "off: the defaults")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (default: the package's autotune_cache.json)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (out = in * 1) three times, "
@@ -253,6 +264,77 @@ def adjoint_bench(a, torch, H, inputs):
     print(json.dumps(line), flush=True)
 
 
+def layered_multi_bench(a, torch, H, inputs, prec):
+    """Sources x frequencies of the layered model: one step = for every
+    frequency, create its handle (the operator depends on the frequency),
+    solve all sources in one batched FGMRES, destroy the handle.  Handle set-up
+    is inside the timed region (whole-job throughput)."""
+    freqs = [float(f) for f in a.freqs.split(",") if f.strip()]
+    ws = [inputs.layered(freq=f, nsrc=a.nrhs) for f in freqs]
+    kfs = [torch.from_numpy(w.kfield()).cuda() for w in ws]
+    bs = [torch.from_numpy(w.sources()).cuda() for w in ws]
+
+    def opts(w):
+        return dict(coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
+                    coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart,
+                    restart=w.restart, tol=w.tol, batch=a.batch, graphs=a.graphs,
+                    vc_tail=a.vc_tail)
+
+    def step(precision, keep=False):
+        infos, xs = [], []
+        for w, kf, b in zip(ws, kfs, bs):
+            S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, k=kf, precision=precision, **opts(w))
+            x, info = S.solve(b)
+            S.close()
+            infos.append(info)
+            if keep:
+                xs.append(x)
+        return infos, xs
+
+    for _ in range(a.warmup):
+        step(prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        infos, _ = step(prec)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if not all(i["converged"] for inf in infos for i in inf):
+        print("bench.py: a solve did not converge", file=sys.stderr)
+        sys.exit(1)
+    nsol = a.nrhs * len(freqs)
+    per_f = {f"{f:g}Hz": {"outer_iters": [min(i["outer_iters"] for i in inf),
+                                          max(i["outer_iters"] for i in inf)],
+                          "inner_iters_sum": sum(i["inner_iters_total"] for i in inf),
+                          "relres_max": max(i["relres"] for i in inf)}
+             for f, inf in zip(freqs, infos)}
+    line = {
+        "metric": "Helmholtz solves/s to 1e-6 rel. residual (sources x frequencies, batched)",
+        "value": nsol * a.steps / el, "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * el / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == H.PREC_FP64 else "f64 (f32 fine-grid V-cycle)",
+        "data": "synthetic",
+        "config": {"workload": f"layered_{ws[0].nx}x{ws[0].ny}_x{a.nrhs}_f"
+                               + "-".join(f"{f:g}" for f in freqs)
+                               + ("" if prec == H.PREC_FP64 else "_mixed"),
+                   "grid": f"{ws[0].nx}x{ws[0].ny}", "h_m": ws[0].hx, "sources": a.nrhs,
+                   "freqs_hz": freqs, "batched": bool(a.batch),
+                   "krylov": f"FGMRES({ws[0].restart}) to {ws[0].tol:g}",
+                   "coarse_solve": f"GMRES({ws[0].coarse_restart}) to {ws[0].coarse_tol:g}",
+                   "per_frequency": per_f},
+    }
+    if prec != H.PREC_FP64:
+        # accuracy against the FP64 solves of the same sources (outside the
+        # timed region)
+        _, x32 = step(prec, keep=True)
+        _, x64 = step(H.PREC_FP64, keep=True)
+        d = max(((u - v).reshape(a.nrhs, -1).norm(dim=1) / v.reshape(a.nrhs, -1).norm(dim=1))
+                .max().item() for u, v in zip(x32, x64))
+        line["config"]["max_rel_diff_to_fp64_solution"] = d
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -278,6 +360,11 @@ def main():
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    if a.workload == "layered" and a.freqs:
+        prec = {"fp64": H.PREC_FP64, "mixed": H.PREC_MIXED,
+                "mixed_c64basis": H.PREC_MIXED_C64BASIS}[a.precision]
+        layered_multi_bench(a, torch, H, inputs, prec)
+        return
     if a.workload == "layered":
         w = inputs.layered(freq=a.freq, nsrc=a.nrhs)
     else:
@@ -286,13 +373,24 @@ def main():
     kf = w.kfield()
     prec = {"fp64": H.PREC_FP64, "mixed": H.PREC_MIXED,
             "mixed_c64basis": H.PREC_MIXED_C64BASIS}[a.precision]
-    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc,
-                 k=None if kf is None else torch.from_numpy(kf).cuda(), kconst=w.kconst,
-                 coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
-                 coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart, restart=w.restart,
-                 tol=w.tol, precision=prec, batch=a.batch, graphs=a.graphs, vc_tail=a.vc_tail)
+    kt = None if kf is None else torch.from_numpy(kf).cuda()
     nrhs = w.nsrc if w.model == "layered" else 1
     b = torch.from_numpy(w.sources() if nrhs > 1 else w.rhs()).cuda()
+    opts = dict(coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
+                coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart, restart=w.restart,
+                tol=w.tol, precision=prec, batch=a.batch, graphs=a.graphs, vc_tail=a.vc_tail)
+    tuned = {}
+    if a.autotune != "off":
+        from paper_2308_06152_amd import autotune
+        grid = (w.nx, w.ny, w.hx, w.hy, w.bc)
+        cache = a.tune_cache or autotune.DEFAULT_CACHE
+        if a.autotune == "run":
+            tuned = autotune.tune(grid, b, opts, k=kt, kconst=w.kconst, cache_path=cache,
+                                  retune=True, log=lambda m: print(m, file=sys.stderr))
+        else:
+            tuned = autotune.lookup(grid, nrhs, opts, kt is not None, cache_path=cache)
+        opts.update(tuned)
+    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, k=kt, kconst=w.kconst, **opts)
     x = torch.zeros_like(b)
     torch.cuda.synchronize()
     for _ in range(a.warmup):
@@ -354,9 +452,10 @@ def main():
                                   H.PREC_MIXED_C64BASIS: ", fine-grid V-cycle in complex64, "
                                                          "complex64 coarse basis"}[prec]),
             "krylov": f"FGMRES({w.restart}) to {w.tol:g}",
-            "coarse_solve": f"GMRES({w.coarse_restart}) to {w.coarse_tol:g}",
+            "coarse_solve": f"GMRES({opts['coarse_restart']}) to {w.coarse_tol:g}",
             "outer_iters": last["outer_iters"], "inner_iters_total": last["inner_iters_total"],
-            "relres": last["relres"], "graphs": bool(a.graphs), "vc_tail": a.vc_tail,
+            "relres": last["relres"], "graphs": bool(opts["graphs"]), "vc_tail": opts["vc_tail"],
+            "autotuned": tuned or None,
             **({"nrhs": nrhs, "batched": bool(a.batch),
                 "outer_iters_max": max(i["outer_iters"] for i in infos[-1]),
                 "inner_iters_sum": sum(i["inner_iters_total"] for i in infos[-1]),
@@ -374,11 +473,8 @@ def main():
     if mixed:
         # accuracy of the mixed-precision solution: against the FP64 solve of
         # the same workload (the FP64 path matches the oracle per solve)
-        S64 = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc,
-                       k=None if kf is None else torch.from_numpy(kf).cuda(), kconst=w.kconst,
-                       coarse_op=w.coarse_op, coarse_mode=H.CMODE_TOL, coarse_tol=w.coarse_tol,
-                       coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart,
-                       restart=w.restart, tol=w.tol, batch=a.batch, vc_tail=a.vc_tail)
+        S64 = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, k=kt, kconst=w.kconst,
+                       **dict(opts, precision=H.PREC_FP64))
         x64, info64 = S64.solve(b)
         S64.close()
         xs, xr = x.reshape(nrhs, -1), x64.reshape(nrhs, -1)

@@ -118,22 +118,25 @@ typedef struct {
                                 level below level 1), with A_2h, that V-cycle,
                                 the products and the updates in FP64. */
     int outer;               /* HELM_OUTER_* (default HELM_OUTER_FGMRES)       */
-    int batch;               /* nrhs > 1 with the FP64 path: 1 (default) = all
-                                right-hand sides in one batched pass (one launch
-                                per kernel for all of them; helm_solve runs one
-                                FGMRES per right-hand side in lockstep, masking
-                                converged ones out); 0 = one after another.
-                                GCR, left GMRES and the mixed-precision option
-                                always go one after another. */
+    int batch;               /* nrhs > 1: 1 (default) = all right-hand sides
+                                in one batched pass (one launch per kernel for
+                                all of them; helm_solve runs one FGMRES per
+                                right-hand side in lockstep, masking converged
+                                ones out), in FP64 or HELM_PREC_MIXED; 0 = one
+                                after another.  GCR, left GMRES and
+                                HELM_PREC_MIXED_C64BASIS always go one after
+                                another. */
     int graphs;              /* 0 (default): every kernel is launched directly.
-                                1: each step of the coarse GMRES (V-cycle, A_2h,
-                                Gram-Schmidt kernels) is captured once per basis
-                                index into a HIP graph and replayed, one launch per
-                                step instead of about twenty (not while kernel
-                                timing is enabled; the batched path launches
-                                directly).  Results are identical either way; on
-                                MI355X the replay measured no faster, the cost of
-                                each dependent kernel being on the device side. */
+                                1: the steps of the coarse GMRES (V-cycle, A_2h,
+                                Gram-Schmidt kernels) are captured into HIP
+                                graphs on first use and replayed: one graph per
+                                basis index for a single right-hand side, one
+                                per chunk of 4 steps (with their read-backs) in
+                                the batched path, which then checks
+                                convergence per chunk (steps computed past a
+                                convergence are not used).  Not while kernel
+                                timing is enabled.  Results are identical
+                                either way. */
     int vc_tail;             /* >0 (default 300000): in the FP64 V-cycle of a
                                 single right-hand side, the levels below the
                                 cycle's top level run fused: the downward passes
@@ -157,7 +160,12 @@ typedef struct {
     int converged;         /* relres <= tol (GMRES_LEFT: the preconditioned
                               residual test of Algorithm 1 was met)             */
     double relres;         /* ||b - A x|| / ||b|| recomputed in FP64 at exit     */
-    double t_solve_ms;     /* wall time of this right-hand side                  */
+    double t_solve_ms;     /* wall time of this right-hand side (of the batch)   */
+    double t_setup_ms;     /* wall time of helm_create for this handle           */
+    double t_coarse_ms;    /* GPU time of the coarse-grid solves (HIP events on
+                              the handle's stream; of the whole batch in a
+                              batched solve)                                    */
+    double t_vcycle_ms;    /* GPU time of the fine-grid CSLP V-cycles (as above) */
 } helm_solve_info;
 
 typedef struct helm_ctx helm_ctx;

@@ -139,14 +139,14 @@ hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const 
 // FP64, ec in FP32 and writes out in FP64 (adding Z v2 in FP64); levels below
 // are FP32 throughout.
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r, cf *rc,
-                          hipStream_t st);
+                          hipStream_t st, Batch bt = Batch{});
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r, cf *rc,
-                          hipStream_t st);
+                          hipStream_t st, Batch bt = Batch{});
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
                         const cf *ec, cd *out, int accumulate, const cd *v2, int zho,
-                        hipStream_t st);
+                        hipStream_t st, Batch bt = Batch{});
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
-                        const cf *ec, cf *out, hipStream_t st);
+                        const cf *ec, cf *out, hipStream_t st, Batch bt = Batch{});
 // The top level of a cycle whose right-hand side is a complex64 vector (the
 // mixed-precision inner Krylov basis), scaled by rs[0].x, with FP64 arithmetic
 // and FP64 levels below.
@@ -173,7 +173,8 @@ hipError_t launch_vc_up_tail(int nt, const Lev *levs, const cd *const *r, const 
 // x = Minv r on the coarsest level (dense inverse, n x n, row major).
 hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_t st,
                            Batch bt = Batch{});
-hipError_t launch_coarsest(int n, const cf *Minv, const cf *r, cf *x, hipStream_t st);
+hipError_t launch_coarsest(int n, const cf *Minv, const cf *r, cf *x, hipStream_t st,
+                           Batch bt = Batch{});
 // vc = Z^T vf, or vc = b - Z^T vf when b != nullptr.
 hipError_t launch_zt(const Lev &Lf, const Lev &Lc, int zho, const cd *vf, const cd *b, cd *vc,
                      hipStream_t st, Batch bt = Batch{});

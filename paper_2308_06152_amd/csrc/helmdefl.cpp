@@ -143,10 +143,13 @@ struct Givens {
 // norms, 1/||u||, least-squares solutions) are SB entries apart.
 constexpr int HB = 2 * PSTRIDE + 1;  // scalars read back per right-hand side
 constexpr int NMASK = 64;            // rotating active-mask buffers
+constexpr int GCHUNK = 4;            // inner steps per captured graph (batched path)
+constexpr int NSLOT = 2 * GCHUNK;    // read-back slots of the batched inner steps
 
 struct BatchWS {
     int B = 0;
     cd *lr[MAXLEV] = {}, *lx[MAXLEV] = {};
+    cf *lrf[MAXLEV] = {}, *lxf[MAXLEV] = {};  // complex64 levels (mixed precision)
     cd *v1 = nullptr, *v2 = nullptr, *tf = nullptr;
     cd *Vc = nullptr, *wc = nullptr, *zc = nullptr;
     cd *part = nullptr, *partn = nullptr;
@@ -155,8 +158,13 @@ struct BatchWS {
     int *dmask = nullptr;  // NMASK device masks of B entries
     int *hmask = nullptr;  // their pinned staging
     int next_mask = 0;
-    cd *hpin = nullptr;    // pinned: 2 read-back slots of B x HB, then y staging B x SB
+    cd *hpin = nullptr;    // pinned: NSLOT read-back slots of B x HB, then y staging B x SB
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // captured chunks of inner steps (opts.graphs): one graph per (first step,
+    // length), reading the active mask from gmask
+    int *gmask = nullptr;
+    std::vector<std::pair<int, hipGraphExec_t>> gchunk;
+    bool graph_off = false;
 };
 
 }  // namespace
@@ -221,6 +229,13 @@ struct helm_ctx {
     long long t_count = 0;
     double t_ms = 0, t_bytes = 0;
 
+    // phase timing of helm_solve: events around the coarse solves (phase 0)
+    // and the fine-grid V-cycles (phase 1) of the solve in progress
+    bool ph_on = false;
+    std::vector<hipEvent_t> ph_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ph_pend[2];
+    double t_setup_ms = 0;  // wall time of helm_create
+
     Lev lev(int l) const
     {
         const LevelH &q = L[l];
@@ -278,6 +293,63 @@ struct Timed {
         h->pend.push_back({a, b, bytes});
     }
 };
+
+// Events bracketing one phase of a solve (no-op unless h->ph_on).
+struct Phase {
+    helm_ctx *h;
+    int k;
+    hipEvent_t a{}, b{};
+    bool on = false;
+    Phase(helm_ctx *h_, int k_) : h(h_), k(k_)
+    {
+        if (!h->ph_on) return;
+        for (int q = 0; q < 2; q++) {
+            hipEvent_t e;
+            if (!h->ph_free.empty()) {
+                e = h->ph_free.back();
+                h->ph_free.pop_back();
+            } else if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                return;
+            }
+            (q == 0 ? a : b) = e;
+        }
+        on = hipEventRecord(a, h->st) == hipSuccess;
+    }
+    ~Phase()
+    {
+        if (!on) return;
+        (void)hipEventRecord(b, h->st);
+        h->ph_pend[k].push_back({a, b});
+    }
+};
+
+// Start phase timing for a solve.
+void phase_begin(helm_ctx *h)
+{
+    h->ph_on = true;
+    for (auto &v : h->ph_pend) v.clear();
+}
+
+// Stop phase timing (after the stream has been synchronised) and return the
+// summed times in ms of the coarse solves and of the fine V-cycles.
+void phase_end(helm_ctx *h, double *t_coarse, double *t_vcycle)
+{
+    double t[2] = {0, 0};
+    for (int k = 0; k < 2; k++) {
+        for (auto &p : h->ph_pend[k]) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) t[k] += ms;
+            h->ph_free.push_back(p.first);
+            h->ph_free.push_back(p.second);
+        }
+        h->ph_pend[k].clear();
+    }
+    (void)hipGetLastError();
+    h->ph_on = false;
+    *t_coarse = t[0];
+    *t_vcycle = t[1];
+}
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -816,7 +888,10 @@ int deflate_one(helm_ctx *h, int mode, const cd *v, cd *w, int *inner)
         Timed tm(h, HELM_K_ZT, 0, 16.0 * nf + 16.0 * nc);
         HCHK(launch_zt(Lf, Lc, h->zho, v, nullptr, h->v1, h->st));
     }
-    RCHK(coarse_solve(h, h->v1, h->v2, inner));
+    {
+        Phase ph(h, 0);
+        RCHK(coarse_solve(h, h->v1, h->v2, inner));
+    }
     if (mode == HELM_DEFL_Q) {
         HCHK(launch_z(Lf, Lc, h->zho, h->v2, w, h->st));
         return HELM_OK;
@@ -827,6 +902,7 @@ int deflate_one(helm_ctx *h, int mode, const cd *v, cd *w, int *inner)
         HCHK(launch_dresid(Lf, Lc, h->zho, v, h->v2, t, h->st));
     }
     if (mode == HELM_DEFL_P) return HELM_OK;
+    Phase ph(h, 1);
     return vcycle(h, 0, t, w, 0, h->v2);
 }
 
@@ -1135,6 +1211,8 @@ void free_batch(BatchWS *W)
     for (int l = 0; l < MAXLEV; l++) {
         dfree(W->lr[l]);
         dfree(W->lx[l]);
+        dfree(W->lrf[l]);
+        dfree(W->lxf[l]);
     }
     for (void *p : {(void *)W->v1, (void *)W->v2, (void *)W->tf,
                     (void *)W->Vc, (void *)W->wc, (void *)W->zc, (void *)W->part,
@@ -1143,6 +1221,9 @@ void free_batch(BatchWS *W)
         dfree(p);
     if (W->hmask) (void)hipHostFree(W->hmask);
     if (W->hpin) (void)hipHostFree(W->hpin);
+    dfree(W->gmask);
+    for (auto &g : W->gchunk)
+        if (g.second) (void)hipGraphExecDestroy(g.second);
     for (auto e : W->ev)
         if (e) (void)hipEventDestroy(e);
     delete W;
@@ -1166,6 +1247,10 @@ int ensure_batch(helm_ctx *h, int B, bool outer)
         for (int l = 1; l < h->nlev && !rc; l++) {
             rc = dalloc(&W->lr[l], b * h->L[l].n());
             if (!rc) rc = dalloc(&W->lx[l], b * h->L[l].n());
+            if (!rc && h->o.precision != HELM_PREC_FP64) {
+                rc = dalloc(&W->lrf[l], b * h->L[l].n());
+                if (!rc) rc = dalloc(&W->lxf[l], b * h->L[l].n());
+            }
         }
         if (!rc) rc = dalloc(&W->v1, b * nc);
         if (!rc) rc = dalloc(&W->v2, b * nc);
@@ -1184,7 +1269,8 @@ int ensure_batch(helm_ctx *h, int B, bool outer)
             W->hmask = nullptr;
             rc = HELM_ENOMEM;
         }
-        if (!rc && hipHostMalloc((void **)&W->hpin, (2 * HB + SB) * b * sizeof(cd)) !=
+        if (!rc) rc = dalloc(&W->gmask, b);
+        if (!rc && hipHostMalloc((void **)&W->hpin, (NSLOT * HB + SB) * b * sizeof(cd)) !=
                        hipSuccess) {
             W->hpin = nullptr;
             rc = HELM_ENOMEM;
@@ -1272,12 +1358,38 @@ int vnorm_b(helm_ctx *h, const cd *v, size_t n, std::vector<double> &out, cd *si
 
 // Batched V-cycle from level l0 (see vcycle); r, z: B contiguous vectors of
 // level l0; rs: per-right-hand-side scale (SB apart) or nullptr.
+// Batched V-cycle from level 0 in complex64 (as vcycle_mixed for every
+// active right-hand side): FP64 r in, FP32 levels, FP64 z out with Z v2.
+int vcycle_mixed_b(helm_ctx *h, const cd *r, cd *z, int accumulate, const cd *v2, const int *dm)
+{
+    BatchWS *W = h->bw;
+    const Batch bt{W->B, dm};
+    const int Lc = h->nlev - 1;
+    for (int l = 0; l < Lc; l++) {
+        if (l == 0)
+            HCHK(launch_vc_down(h->lev(0), h->lev(1), h->shift, h->o.omega, r, W->lrf[1], h->st,
+                                bt));
+        else
+            HCHK(launch_vc_down(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, W->lrf[l],
+                                W->lrf[l + 1], h->st, bt));
+    }
+    HCHK(launch_coarsest(h->ncoarsest, h->cinvf, W->lrf[Lc], W->lxf[Lc], h->st, bt));
+    for (int l = Lc - 1; l >= 1; l--)
+        HCHK(launch_vc_up(h->lev(l), h->lev(l + 1), h->shift, h->o.omega, W->lrf[l],
+                          W->lxf[l + 1], W->lxf[l], h->st, bt));
+    HCHK(launch_vc_up(h->lev(0), h->lev(1), h->shift, h->o.omega, r, W->lxf[1], z, accumulate, v2,
+                      h->zho, h->st, bt));
+    return HELM_OK;
+}
+
 int vcycle_b(helm_ctx *h, int l0, const cd *r, cd *z, int accumulate, const cd *v2,
              const cd *rs, const int *dm)
 {
     BatchWS *W = h->bw;
     const Batch bt{W->B, dm};
     const int Lc = h->nlev - 1;
+    if (l0 == 0 && h->o.precision != HELM_PREC_FP64 && !rs)
+        return vcycle_mixed_b(h, r, z, accumulate, v2, dm);
     if (l0 == Lc) {
         const size_t n = h->L[Lc].n();
         if (!accumulate && !rs) {
@@ -1324,6 +1436,16 @@ int coarse_apply_b(helm_ctx *h, const cd *x, const cd *b, cd *y, const int *dm)
 // Lazily normalised Arnoldi step of the batched inner GMRES (as
 // arnoldi_lazy_enqueue, for every active right-hand side): basis slot j1
 // already holds A z; projections and the norm go to read-back slot `slot`.
+// Copy every right-hand side's step scalars (projections of both passes and
+// the norm) into read-back slot `slot` of the pinned buffer.
+int readback_b(helm_ctx *h, int slot)
+{
+    BatchWS *W = h->bw;
+    HCHK(hipMemcpy2DAsync(W->hpin + (size_t)slot * HB * W->B, HB * sizeof(cd), W->hbuf,
+                          SB * sizeof(cd), HB * sizeof(cd), W->B, hipMemcpyDeviceToHost, h->st));
+    return HELM_OK;
+}
+
 int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm, int nact)
 {
     BatchWS *W = h->bw;
@@ -1346,10 +1468,7 @@ int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm, int nact)
     HCHK(launch_reduce(W->part, nb, j1, h2, 0, h1, j1, W->sig, j1, nullptr, h->st, bt));
     HCHK(launch_mupdate(w, W->Vc, ld, j1, h2, n, W->partn, h1, j1, W->sig, h->st, bt, n, n));
     HCHK(launch_reduce(W->partn, nbu, 1, nr, 2, nullptr, 0, nullptr, 0, W->sig + j1, h->st, bt));
-    HCHK(hipMemcpy2DAsync(W->hpin + (size_t)slot * HB * W->B, HB * sizeof(cd), W->hbuf,
-                          SB * sizeof(cd), HB * sizeof(cd), W->B, hipMemcpyDeviceToHost, h->st));
-    HCHK(hipEventRecord(W->ev[slot], h->st));
-    return HELM_OK;
+    return readback_b(h, slot);
 }
 
 // Projections (both passes summed) and norm of right-hand side b from a
@@ -1371,12 +1490,67 @@ int inner_step_b(helm_ctx *h, int j, int slot, const int *dm, int nact)
     return arnoldi_lazy_b(h, j + 1, slot, dm, nact);
 }
 
+// Copy an active mask into the fixed device mask the captured chunks read
+// (through the rotating pinned staging of upload_mask).
+int upload_gmask(helm_ctx *h, const std::vector<char> &act)
+{
+    BatchWS *W = h->bw;
+    if (W->next_mask == NMASK) {
+        HCHK(hipStreamSynchronize(h->st));
+        W->next_mask = 0;
+    }
+    int *hm = W->hmask + (size_t)(W->next_mask++) * W->B;
+    for (int b = 0; b < W->B; b++) hm[b] = act[b] ? 1 : 0;
+    HCHK(hipMemcpyAsync(W->gmask, hm, W->B * sizeof(int), hipMemcpyHostToDevice, h->st));
+    return HELM_OK;
+}
+
+// Inner steps j0 .. j0 + len - 1 of the batched coarse GMRES as one graph
+// (captured on first use, then replayed): each step's kernels for the
+// right-hand sides that W->gmask marks active, and its read-back into slot
+// sbase + (step - j0).  The chunk's event is recorded after it as stream work.
+// Returns HELM_EHIP with W->graph_off set when capture is not possible; the
+// caller then launches the steps directly.
+int chunk_b(helm_ctx *h, int j0, int len, int sbase, int par)
+{
+    BatchWS *W = h->bw;
+    const int key = j0 * 64 + len * 2 + (sbase ? 1 : 0);
+    hipGraphExec_t ex = nullptr;
+    for (auto &g : W->gchunk)
+        if (g.first == key) ex = g.second;
+    if (!ex) {
+        if (hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            W->graph_off = true;
+            return HELM_EHIP;
+        }
+        int rc = HELM_OK;
+        for (int s = 0; s < len && rc == HELM_OK; s++)
+            rc = inner_step_b(h, j0 + s, sbase + s, W->gmask, W->B);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(h->st, &g);
+        if (rc == HELM_OK && ec == hipSuccess && g &&
+            hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+            W->gchunk.push_back({key, ex});
+        } else {
+            (void)hipGetLastError();
+            ex = nullptr;
+            W->graph_off = true;
+        }
+        if (g) (void)hipGraphDestroy(g);
+        if (!ex) return HELM_EHIP;
+    }
+    HCHK(hipGraphLaunch(ex, h->st));
+    HCHK(hipEventRecord(W->ev[par], h->st));
+    return HELM_OK;
+}
+
 // Upload per-right-hand-side least-squares solutions (y[b], zero-padded to
 // jmax) into W->ydev.
 int upload_y_b(helm_ctx *h, const std::vector<std::vector<zc>> &y, int jmax)
 {
     BatchWS *W = h->bw;
-    cd *stg = W->hpin + (size_t)2 * HB * W->B;
+    cd *stg = W->hpin + (size_t)NSLOT * HB * W->B;
     for (int b = 0; b < W->B; b++)
         for (int i = 0; i < jmax; i++) {
             const zc v = i < (int)y[b].size() ? y[b][i] : zc(0);
@@ -1455,15 +1629,14 @@ int coarse_solve_b(helm_ctx *h, const cd *bvec, cd *x, const std::vector<char> &
         }
         const int steps = std::min(m, cap - itmin);
         int nact = nlive;
-        RCHK(inner_step_b(h, 0, 0, dm, nact));
-        for (int j = 0; j < steps; j++) {
-            if (j + 1 < steps) RCHK(inner_step_b(h, j + 1, (j + 1) & 1, dm, nact));
-            HCHK(hipEventSynchronize(W->ev[j & 1]));
-            bool changed = false;
+        // the columns of step j (read-back slot `slot`) for every stepping
+        // right-hand side; returns the number still stepping
+        bool changed = false;
+        auto take_step = [&](int j, int slot) {
             int nstep = 0;
             for (int b = 0; b < B; b++) {
                 if (!stepm[b]) continue;
-                const double hn = read_col(W, j & 1, b, j + 1, col.data());
+                const double hn = read_col(W, slot, b, j + 1, col.data());
                 const double res = gv[b].add_column(j, col.data(), hn);
                 iters[b]++;
                 jend[b] = j + 1;
@@ -1476,11 +1649,57 @@ int coarse_solve_b(helm_ctx *h, const cd *bvec, cd *x, const std::vector<char> &
                     nstep++;
                 }
             }
-            if (nstep == 0) break;
-            if (changed) {
-                dm = upload_mask(h, stepm);
-                MCHK(dm);
-                nact = nstep;
+            return nstep;
+        };
+        bool graphs = h->o.graphs && !W->graph_off && h->t_cls < 0;
+        int rc = HELM_OK;
+        if (graphs) {
+            RCHK(upload_gmask(h, stepm));
+            rc = chunk_b(h, 0, std::min(GCHUNK, steps), 0, 0);
+            // a chunk that cannot be captured: this and later cycles launch
+            // their steps directly
+            if (rc != HELM_OK && W->graph_off) graphs = false;
+        }
+        if (graphs) {
+            // chunks of GCHUNK steps replayed from graphs; chunk c + 1 is
+            // queued before the host reads chunk c (its steps past a
+            // convergence are not used), and a new mask reaches the chunks
+            // queued after it
+            for (int c0 = 0; rc == HELM_OK && c0 < steps; c0 += GCHUNK) {
+                const int len = std::min(GCHUNK, steps - c0), par = (c0 / GCHUNK) & 1;
+                if (c0 + GCHUNK < steps) {
+                    if (changed) {
+                        RCHK(upload_gmask(h, stepm));
+                        changed = false;
+                    }
+                    rc = chunk_b(h, c0 + GCHUNK, std::min(GCHUNK, steps - c0 - GCHUNK),
+                                 (par ^ 1) * GCHUNK, par ^ 1);
+                    if (rc != HELM_OK) break;
+                }
+                HCHK(hipEventSynchronize(W->ev[par]));
+                int nstep = 1;
+                for (int q = 0; q < len && nstep > 0; q++) nstep = take_step(c0 + q, par * GCHUNK + q);
+                if (nstep == 0) break;
+            }
+            if (rc != HELM_OK) return rc;
+        } else {
+            if (h->o.graphs) HCHK(hipStreamSynchronize(h->st));  // after a failed capture
+            RCHK(inner_step_b(h, 0, 0, dm, nact));
+            HCHK(hipEventRecord(W->ev[0], h->st));
+            for (int j = 0; j < steps; j++) {
+                if (j + 1 < steps) {
+                    RCHK(inner_step_b(h, j + 1, (j + 1) & 1, dm, nact));
+                    HCHK(hipEventRecord(W->ev[(j + 1) & 1], h->st));
+                }
+                HCHK(hipEventSynchronize(W->ev[j & 1]));
+                changed = false;
+                const int nstep = take_step(j, j & 1);
+                if (nstep == 0) break;
+                if (changed) {
+                    dm = upload_mask(h, stepm);
+                    MCHK(dm);
+                    nact = nstep;
+                }
             }
         }
         // x += V-cycle(sum_i y_i v_i) for every right-hand side of the cycle
@@ -1514,7 +1733,10 @@ int deflate_b(helm_ctx *h, int mode, const cd *v, cd *w, const std::vector<char>
     MCHK(dm);
     const Batch bt{W->B, dm};
     HCHK(launch_zt(Lf, Lc, h->zho, v, nullptr, W->v1, h->st, bt));
-    RCHK(coarse_solve_b(h, W->v1, W->v2, act, inner));
+    {
+        Phase ph(h, 0);
+        RCHK(coarse_solve_b(h, W->v1, W->v2, act, inner));
+    }
     dm = upload_mask(h, act);
     MCHK(dm);
     const Batch bt2{W->B, dm};
@@ -1525,6 +1747,7 @@ int deflate_b(helm_ctx *h, int mode, const cd *v, cd *w, const std::vector<char>
     cd *t = mode == HELM_DEFL_P ? w : W->tf;
     HCHK(launch_dresid(Lf, Lc, h->zho, v, W->v2, t, h->st, bt2));
     if (mode == HELM_DEFL_P) return HELM_OK;
+    Phase ph(h, 1);
     return vcycle_b(h, 0, W->tf, w, 0, W->v2, nullptr, dm);
 }
 
@@ -1795,6 +2018,12 @@ void release(helm_ctx *h)
         (void)hipEventDestroy(p.b);
     }
     for (auto e : h->ev_free) (void)hipEventDestroy(e);
+    for (auto e : h->ph_free) (void)hipEventDestroy(e);
+    for (auto &v : h->ph_pend)
+        for (auto &p : v) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
     free_batch(h->bw);
     dfree(h->adjb);
     delete h;
@@ -1834,6 +2063,7 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
         o.precision != HELM_PREC_MIXED_C64BASIS)
         return HELM_EINVAL;
     if (!k_dev && (!std::isfinite(k_const) || k_const < 0)) return HELM_ENONFINITE;
+    const auto t_start = std::chrono::steady_clock::now();
 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return HELM_EHIP;
@@ -1949,10 +2179,14 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
             hipSuccess)
             rc = HELM_EHIP;
     }
+    if (!rc && hipStreamSynchronize(h->st) != hipSuccess) rc = HELM_EHIP;
     if (rc) {
         release(h);
         return rc;
     }
+    h->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                              t_start)
+                        .count();
     *out = h;
     return HELM_OK;
 }
@@ -2074,10 +2308,10 @@ int helm_apply(helm_ctx *h, const void *x, void *y, int nrhs)
 }
 
 // Several right-hand sides go through the batched kernels when the option
-// asks for it and the FP64 path is in use.
+// asks for it (FP64, or the complex64 fine-grid V-cycle of HELM_PREC_MIXED).
 static bool batched(const helm_ctx *h, int nrhs)
 {
-    return nrhs > 1 && h->o.batch && h->o.precision == HELM_PREC_FP64;
+    return nrhs > 1 && h->o.batch && h->o.precision != HELM_PREC_MIXED_C64BASIS;
 }
 
 int cslp_vcycle(helm_ctx *h, const void *r, void *z, int nrhs)
@@ -2129,25 +2363,46 @@ int deflate_apply(helm_ctx *h, int mode, const void *v, void *w, int nrhs)
     return HELM_OK;
 }
 
+// The phase times of a solve (or of a batched solve, shared by its right-hand
+// sides) into info[0..cnt).
+static void set_phases(helm_ctx *h, helm_solve_info *info, int cnt)
+{
+    double tc = 0, tv = 0;
+    phase_end(h, &tc, &tv);
+    if (!info) return;
+    for (int q = 0; q < cnt; q++) {
+        info[q].t_setup_ms = h->t_setup_ms;
+        info[q].t_coarse_ms = tc;
+        info[q].t_vcycle_ms = tv;
+    }
+}
+
 static int solve_dispatch(helm_ctx *h, const void *b, void *x, int nrhs, helm_solve_info *info)
 {
     const size_t n = h->L[0].n();
     int worst = HELM_OK;
     try {
-        if (batched(h, nrhs) && h->o.outer == HELM_OUTER_FGMRES)
-            return solve_b(h, (const cd *)b, (cd *)x, nrhs, info);
+        if (batched(h, nrhs) && h->o.outer == HELM_OUTER_FGMRES) {
+            phase_begin(h);
+            const int rc = solve_b(h, (const cd *)b, (cd *)x, nrhs, info);
+            set_phases(h, info, nrhs);
+            return rc;
+        }
         RCHK(ensure_outer(h));
         for (int q = 0; q < nrhs; q++) {
             const cd *bq = (const cd *)b + q * n;
             cd *xq = (cd *)x + q * n;
             helm_solve_info *iq = info ? info + q : nullptr;
+            phase_begin(h);
             const int rc = h->o.outer == HELM_OUTER_GCR         ? solve_gcr(h, bq, xq, iq)
                            : h->o.outer == HELM_OUTER_GMRES_LEFT ? solve_left(h, bq, xq, iq)
                                                                  : solve_one(h, bq, xq, iq);
+            set_phases(h, iq, 1);
             if (rc != HELM_OK && rc != HELM_ENOCONV) return rc;
             if (rc == HELM_ENOCONV) worst = rc;
         }
     } catch (...) {
+        h->ph_on = false;
         return HELM_ENOMEM;
     }
     return worst;

@@ -12,7 +12,12 @@
 //    XCDs, so tiles are renumbered to give every XCD a contiguous band of the
 //    grid, keeping vertical halos in that XCD's L2;
 //  * reductions are deterministic: fixed per-block partial sums, then a fixed
-//    tree in a second kernel.
+//    tree in a second kernel;
+//  * no implicit contraction of a multiply and an add into an FMA: every FMA
+//    is written out, so an expression gives the same bits in every kernel
+//    that evaluates it (the fused V-cycle tails and the per-level passes, the
+//    batched and the single kernels), whatever the instruction scheduling.
+#pragma clang fp contract(off)
 #include "hd_common.h"
 
 #include <type_traits>
@@ -161,37 +166,50 @@ __device__ __forceinline__ cd prolong_at(const Lev &Lc, const cd *__restrict__ v
     return s;
 }
 
-// The same sum with the coarse values read from an LDS tile whose entry
-// [J - cj0][I - ci0] holds vc at coarse node (I, J) (the tile must cover
-// every coarse node the rule reaches from (i, j)).
+// (Z v) at a fine node from an LDS tile of the coarse values around it, whose
+// entries outside the grid or at non-unknowns hold 0: (a, b) is the fine node
+// relative to the tile origin's fine image, so its coarse node (a >> 1,
+// b >> 1) must have a tile neighbour on each side.  Each axis takes 3 taps,
+// relative to that coarse node, with weights
+//   even fine index: (w2, w0, w2) = (1, 6, 1)/8 Bezier, (0, 1, 0) linear;
+//   odd  fine index: (0, 1/2, 1/2);
+// no per-node index arrays, so nothing is kept in scratch memory.
 template <int W>
-__device__ __forceinline__ cd prolong_tile(const Lev &Lc, const cd (*t)[W], int ci0, int cj0,
-                                           int i, int j, int zho)
+__device__ __forceinline__ cd zv2_tile(const cd (*t)[W], int a, int b, int zho)
 {
-    int Ix[3], Jy[3];
-    double wx[3], wy[3];
-    const int nxw = zrule(i, zho, Ix, wx), nyw = zrule(j, zho, Jy, wy);
-    cd s = czero();
-    for (int b = 0; b < nyw; b++) {
-        const int J = Jy[b];
-        if (J < 0 || J >= Lc.ny) continue;
-        for (int a = 0; a < nxw; a++) {
-            const int I = Ix[a];
-            if (I < 0 || I >= Lc.nx || !unknown(Lc, I, J)) continue;
-            caxpy(s, wx[a] * wy[b], t[J - cj0][I - ci0]);
-        }
+    const int A = a >> 1, B = b >> 1;
+    const double w0 = zho ? 0.75 : 1.0, w2 = zho ? 0.125 : 0.0;
+    const double xm = (a & 1) ? 0.0 : w2, x0 = (a & 1) ? 0.5 : w0, xp = (a & 1) ? 0.5 : w2;
+    const double ym = (b & 1) ? 0.0 : w2, y0 = (b & 1) ? 0.5 : w0, yp = (b & 1) ? 0.5 : w2;
+    cd r[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const cd *row = t[B - 1 + d];
+        cd v = cscal(x0, row[A]);
+        caxpy(v, xm, row[A - 1]);
+        caxpy(v, xp, row[A + 1]);
+        r[d] = v;
     }
-    return s;
+    cd z = cscal(y0, r[1]);
+    caxpy(z, ym, r[0]);
+    caxpy(z, yp, r[2]);
+    return z;
 }
 
 // ------------------------------------------------------------------------
 // 5-point operator: y = op x  or  y = b - op x
-// Block: 64 x 4 threads; each thread owns one column of a 64 x 16 tile and
-// streams 4 rows, keeping south/centre/north in registers.
+// Each wave streams a strip of A5_RPW rows of 64 consecutive columns and
+// writes the 62 in the middle (lanes 1..62): every row is one 1 KB load, the
+// west/east neighbours come from the adjacent lanes by DPP shifts, and the
+// north/south ones from the rows before and after in registers.  A block is
+// 4 waves stacked over 4 * A5_RPW rows; rows are loaded unconditionally from
+// a clamped address A5_AHEAD rows ahead of their use and zeroed outside the
+// grid (and at Dirichlet nodes) by a 0/1 factor, so each wave keeps many rows
+// in flight.
 // ------------------------------------------------------------------------
-constexpr int AP_TX = 64, AP_TY = 16, AP_RPT = 4;
+constexpr int A5_TX = 62, A5_RPW = 16, A5_AHEAD = 12;
 
-template <bool RESID>
+template <bool RESID, bool VARK>
 __global__ __launch_bounds__(256) void k_apply5(Lev L, cd s, const cd *__restrict__ x,
                                                 const cd *__restrict__ b, cd *__restrict__ y,
                                                 int tiles_x, Batch bt)
@@ -203,31 +221,58 @@ __global__ __launch_bounds__(256) void k_apply5(Lev L, cd s, const cd *__restric
         if (RESID) b += off;
         y += off;
     }
+    const int lane = threadIdx.x & 63;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int i = (t % tiles_x) * AP_TX + (threadIdx.x & 63);
-    const int j0 = (t / tiles_x) * AP_TY + (threadIdx.x >> 6) * AP_RPT;
-    if (i >= L.nx || j0 >= L.ny) return;
-    const int nx = L.nx;
-    cd xs = (j0 > 0) ? x[(size_t)(j0 - 1) * nx + i] : czero();
-    cd xc = x[(size_t)j0 * nx + i];
-#pragma unroll
-    for (int r = 0; r < AP_RPT; r++) {
-        const int j = j0 + r;
-        if (j >= L.ny) break;
-        const size_t p = (size_t)j * nx + i;
-        const cd xn = (j + 1 < L.ny) ? x[p + nx] : czero();
-        cd ap;
-        double aw, ae, as, an;
-        cd v = czero();
-        if (coef5(L, s, i, j, ap, aw, ae, as, an)) {
-            v = cmul(ap, xc);
-            if (aw != 0.0) caxpy(v, aw, x[p - 1]);
-            if (ae != 0.0) caxpy(v, ae, x[p + 1]);
-            if (as != 0.0) caxpy(v, as, xs);
-            if (an != 0.0) caxpy(v, an, xn);
-            if (RESID) v = csub(b[p], v);
+    const int i = (t % tiles_x) * A5_TX - 1 + lane;
+    const int j0 = (t / tiles_x) * (4 * A5_RPW) + (threadIdx.x >> 6) * A5_RPW;
+    const int nx = L.nx, ny = L.ny;
+    if (j0 >= ny) return;  // the whole wave: no row here
+    const bool colin = i >= 0 && i < nx;
+    const int ic = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+    const bool outc = lane >= 1 && lane <= A5_TX && colin;
+    constexpr int NR = A5_RPW + 2;  // rows j0-1 .. j0+A5_RPW
+    cd xb[NR], bb[RESID ? A5_RPW : 1];
+    double kb[VARK ? A5_RPW : 1];
+    auto load_row = [&](int q) {
+        const int jj = j0 - 1 + q;
+        const size_t p = (size_t)(jj < 0 ? 0 : (jj >= ny ? ny - 1 : jj)) * nx + ic;
+        xb[q] = x[p];
+        if (q >= 1 && q <= A5_RPW) {
+            if (VARK) kb[q - 1] = L.k[p];
+            if (RESID) bb[q - 1] = b[p];
         }
-        y[p] = v;
+    };
+#pragma unroll
+    for (int q = 0; q < A5_AHEAD && q < NR; q++) load_row(q);
+    // keep the loads above ahead of the arithmetic below
+    __builtin_amdgcn_sched_barrier(0);
+    cd xs = czero(), xc = czero();
+#pragma unroll
+    for (int q = 0; q < NR; q++) {
+        if (q + A5_AHEAD < NR) load_row(q + A5_AHEAD);
+        const int jj = j0 - 1 + q;
+        const double m = colin && jj >= 0 && jj < ny && unknown(L, ic, jj) ? 1.0 : 0.0;
+        const cd xn = cscal(m, xb[q]);
+        if (q >= 2) {
+            // output row j = jj - 1: south xs, centre xc, north xn
+            const int j = jj - 1;
+            const cd xw = lane_from(xc, true), xe = lane_from(xc, false);
+            if (outc && j < ny) {
+                cd ap;
+                double aw, ae, as, an;
+                cd v = czero();
+                const double kv = VARK ? kb[q - 2] : L.kc;
+                if (coef5k(L, s, i, j, kv, ap, aw, ae, as, an)) {
+                    v = cmul(ap, xc);
+                    caxpy(v, aw, xw);
+                    caxpy(v, ae, xe);
+                    caxpy(v, as, xs);
+                    caxpy(v, an, xn);
+                    if (RESID) v = csub(bb[q - 2], v);
+                }
+                y[(size_t)j * nx + i] = v;
+            }
+        }
         xs = xc;
         xc = xn;
     }
@@ -236,12 +281,19 @@ __global__ __launch_bounds__(256) void k_apply5(Lev L, cd s, const cd *__restric
 hipError_t launch_apply5(const Lev &L, cd s, const cd *x, const cd *b, cd *y, hipStream_t st,
                          Batch bt)
 {
-    const int tx = cdiv(L.nx, AP_TX), ty = cdiv(L.ny, AP_TY);
+    const int tx = cdiv(L.nx, A5_TX), ty = cdiv(L.ny, 4 * A5_RPW);
     const dim3 g(tx * ty, bt.B);
-    if (b)
-        k_apply5<true><<<g, 256, 0, st>>>(L, s, x, b, y, tx, bt);
-    else
-        k_apply5<false><<<g, 256, 0, st>>>(L, s, x, b, y, tx, bt);
+    if (L.k) {
+        if (b)
+            k_apply5<true, true><<<g, 256, 0, st>>>(L, s, x, b, y, tx, bt);
+        else
+            k_apply5<false, true><<<g, 256, 0, st>>>(L, s, x, b, y, tx, bt);
+    } else {
+        if (b)
+            k_apply5<true, false><<<g, 256, 0, st>>>(L, s, x, b, y, tx, bt);
+        else
+            k_apply5<false, false><<<g, 256, 0, st>>>(L, s, x, b, y, tx, bt);
+    }
     HD_LAUNCH_CHECK();
 }
 
@@ -480,15 +532,15 @@ hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, cons
 }
 
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r, cf *rc,
-                          hipStream_t st)
+                          hipStream_t st, Batch bt)
 {
-    return vc_down_t<double, float>(Lf, Lc, s, omega, r, nullptr, rc, st, Batch{});
+    return vc_down_t<double, float>(Lf, Lc, s, omega, r, nullptr, rc, st, bt);
 }
 
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r, cf *rc,
-                          hipStream_t st)
+                          hipStream_t st, Batch bt)
 {
-    return vc_down_t<float, float>(Lf, Lc, s, omega, r, nullptr, rc, st, Batch{});
+    return vc_down_t<float, float>(Lf, Lc, s, omega, r, nullptr, rc, st, bt);
 }
 
 hipError_t launch_vc_down(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
@@ -783,16 +835,19 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
         }
     }
     // v2 on the same coarse tile as ec: every coarse node the Z rule reaches
-    // from the owned fine nodes (prolong_at skips those outside the grid or
-    // not unknowns, so their entries are never read)
+    // from the owned fine nodes; nodes outside the grid or not unknowns hold
+    // 0, as the rule leaves them out (zeroed by a 0/1 factor, see above)
     cd v2l[V2 ? NKC : 1];
+    double mv2[V2 ? NKC : 1];
     if constexpr (V2) {
 #pragma unroll
         for (int kq = 0; kq < NKC; kq++) {
             const int q = threadIdx.x + 256 * kq;
             const int I = ci0 + q % VU_CW, J = cj0 + q / VU_CW;
-            const bool in = q < NC && I >= 0 && I < Lc.nx && J >= 0 && J < Lc.ny;
+            const bool in = q < NC && I >= 0 && I < Lc.nx && J >= 0 && J < Lc.ny &&
+                            unknown(Lc, I, J);
             v2l[kq] = v2[in ? (size_t)J * Lc.nx + I : 0];
+            mv2[kq] = in ? 1.0 : 0.0;
         }
     }
     {
@@ -817,7 +872,7 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
         const int q = threadIdx.x + 256 * kq;
         if (q < NC) se[q / VU_CW][q % VU_CW] = el[kq];
         if constexpr (V2)
-            if (q < NC) sv2[q / VU_CW][q % VU_CW] = v2l[kq];
+            if (q < NC) sv2[q / VU_CW][q % VU_CW] = cscal(mv2[kq], v2l[kq]);
     }
     __syncthreads();
     // ---- x2 = omega D^-1 r + P ec at the owned nodes and the halo node
@@ -865,7 +920,7 @@ __global__ __launch_bounds__(256) void k_vc_up(Lev Lf, Lev Lc, cd s, double omeg
             caxpy(m, as, sx2[bb - 1][a]);
             caxpy(m, an, sx2[bb + 1][a]);
             v = cvt<RO>(cadd(sx2[bb][a], cmul(wv, csub(rown[rr], m))));
-            if constexpr (V2) v = cadd(v, cvt<RO>(prolong_tile(Lc, sv2, ci0, cj0, i, j, zho)));
+            if constexpr (V2) v = cadd(v, cvt<RO>(zv2_tile(sv2, i - 2 * ci0, j - 2 * cj0, zho)));
         }
         if (accumulate) v = cadd(v, oold[rr]);
         out[p] = v;
@@ -1107,17 +1162,17 @@ hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const 
 
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cd *r,
                         const cf *ec, cd *out, int accumulate, const cd *v2, int zho,
-                        hipStream_t st)
+                        hipStream_t st, Batch bt)
 {
     return vc_up_t<double, float, double>(Lf, Lc, s, omega, r, nullptr, ec, out, accumulate, v2,
-                                          zho, st, Batch{});
+                                          zho, st, bt);
 }
 
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
-                        const cf *ec, cf *out, hipStream_t st)
+                        const cf *ec, cf *out, hipStream_t st, Batch bt)
 {
     return vc_up_t<float, float, float>(Lf, Lc, s, omega, r, nullptr, ec, out, 0, nullptr, 0, st,
-                                        Batch{});
+                                        bt);
 }
 
 hipError_t launch_vc_up(const Lev &Lf, const Lev &Lc, cd s, double omega, const cf *r,
@@ -1177,20 +1232,29 @@ hipError_t launch_coarsest(int n, const cd *Minv, const cd *r, cd *x, hipStream_
     HD_LAUNCH_CHECK();
 }
 
-hipError_t launch_coarsest(int n, const cf *Minv, const cf *r, cf *x, hipStream_t st)
+hipError_t launch_coarsest(int n, const cf *Minv, const cf *r, cf *x, hipStream_t st, Batch bt)
 {
-    k_coarsest<float><<<cdiv(n, 4), 256, 0, st>>>(n, Minv, r, x, Batch{});
+    k_coarsest<float><<<dim3(cdiv(n, 4), bt.B), 256, 0, st>>>(n, Minv, r, x, bt);
     HD_LAUNCH_CHECK();
 }
 
 // ------------------------------------------------------------------------
 // Deflation restriction vc = Z^T vf (or b - Z^T vf): [1 4 6 4 1]/8 (Bezier)
-// or 1/2 [1 2 1] (linear) per axis, centred on fine node (2I, 2J).  One block
-// computes a 32 x 8 coarse tile from a 67 x 19 fine LDS tile; the x pass is
-// done first into LDS, then the y pass.
+// or 1/2 [1 2 1] (linear) per axis, centred on fine node (2I, 2J); the x pass
+// first, then the y pass.
+// (ZT_CX x ZT_CY is the coarse tile of the one-launch Galerkin operator
+// below, which computes a 67 x 19 fine region per block.)
 // ------------------------------------------------------------------------
 constexpr int ZT_CX = 32, ZT_CY = 8;
 constexpr int ZT_W = 2 * ZT_CX + 3, ZT_H = 2 * ZT_CY + 3;
+
+// Streaming form: lane l of a wave holds fine column i = c0 + l (c0 even) of
+// 19 consecutive fine rows, loaded A5_AHEAD rows ahead; each row is filtered
+// along x with the neighbours at distance 1 and 2 from adjacent lanes (DPP
+// shifts), a rolling window of 5 filtered rows gives the y filter, and the
+// lanes on even fine columns 2..61 write coarse columns I = i / 2 (30 per
+// wave) of 8 coarse rows.  A block is 4 waves stacked over 32 coarse rows.
+constexpr int ZS_CX = 30, ZS_RPW = 8;
 
 template <bool RESID>
 __global__ __launch_bounds__(256) void k_zt(Lev Lf, Lev Lc, int zho, const cd *__restrict__ vf,
@@ -1204,54 +1268,61 @@ __global__ __launch_bounds__(256) void k_zt(Lev Lf, Lev Lc, int zho, const cd *_
         if (RESID) b += blockIdx.y * nc;
         vc += blockIdx.y * nc;
     }
-    __shared__ cd sv[ZT_H][ZT_W];
-    __shared__ cd sx[ZT_H][ZT_CX];
+    const int lane = threadIdx.x & 63;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int I0 = (t % tiles_x) * ZT_CX, J0 = (t / tiles_x) * ZT_CY;
-    const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;
+    const int i = (t % tiles_x) * (2 * ZS_CX) - 2 + lane;
+    const int J0 = (t / tiles_x) * (4 * ZS_RPW) + (threadIdx.x >> 6) * ZS_RPW;
+    const int nx = Lf.nx, ny = Lf.ny;
+    if (J0 >= Lc.ny) return;  // the whole wave: no coarse row here
+    const bool colin = i >= 0 && i < nx;
+    const int ic = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+    const int I = i >> 1;
+    const bool outc = lane >= 2 && lane <= 2 * ZS_CX + 1 && !(i & 1) && I < Lc.nx;
+    constexpr int NR = 2 * ZS_RPW + 3;  // fine rows 2 J0 - 2 .. 2 J0 + 2 ZS_RPW
+    cd vb[NR];
+    auto load_row = [&](int q) {
+        const int jj = 2 * J0 - 2 + q;
+        vb[q] = vf[(size_t)(jj < 0 ? 0 : (jj >= ny ? ny - 1 : jj)) * nx + ic];
+    };
 #pragma unroll
-    for (int kq = 0; kq < (ZT_W * ZT_H + 255) / 256; kq++) {
-        const int q = threadIdx.x + 256 * kq;
-        if (q >= ZT_W * ZT_H) continue;
-        const int a = q % ZT_W, bb = q / ZT_W;
-        const int fi = fi0 + a, fj = fj0 + bb;
-        cd v = czero();
-        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny && unknown(Lf, fi, fj))
-            v = vf[(size_t)fj * Lf.nx + fi];
-        sv[bb][a] = v;
-    }
-    __syncthreads();
+    for (int q = 0; q < A5_AHEAD && q < NR; q++) load_row(q);
+    __builtin_amdgcn_sched_barrier(0);
     const double w0 = zho ? 0.75 : 1.0, w1 = 0.5, w2 = zho ? 0.125 : 0.0;
+    cd X[5];
 #pragma unroll
-    for (int kq = 0; kq < (ZT_CX * ZT_H + 255) / 256; kq++) {
-        const int q = threadIdx.x + 256 * kq;
-        if (q >= ZT_CX * ZT_H) continue;
-        const int c = q % ZT_CX, bb = q / ZT_CX;
-        const int a = 2 * c + 2;
-        cd v = cscal(w0, sv[bb][a]);
-        caxpy(v, w1, cadd(sv[bb][a - 1], sv[bb][a + 1]));
-        if (zho) caxpy(v, w2, cadd(sv[bb][a - 2], sv[bb][a + 2]));
-        sx[bb][c] = v;
+    for (int q = 0; q < NR; q++) {
+        if (q + A5_AHEAD < NR) load_row(q + A5_AHEAD);
+        const int jj = 2 * J0 - 2 + q;
+        const double m = colin && jj >= 0 && jj < ny && unknown(Lf, ic, jj) ? 1.0 : 0.0;
+        const cd c = cscal(m, vb[q]);
+        const cd l1 = lane_from(c, true), r1 = lane_from(c, false);
+        const cd l2 = lane_from(l1, true), r2 = lane_from(r1, false);
+        cd xv = cscal(w0, c);
+        caxpy(xv, w1, cadd(l1, r1));
+        if (zho) caxpy(xv, w2, cadd(l2, r2));
+#pragma unroll
+        for (int d = 0; d < 4; d++) X[d] = X[d + 1];
+        X[4] = xv;
+        if (q >= 4 && !(q & 1)) {
+            const int J = J0 + (q - 4) / 2;
+            if (outc && J < Lc.ny) {
+                cd v = czero();
+                if (unknown(Lc, I, J)) {
+                    v = cscal(w0, X[2]);
+                    caxpy(v, w1, cadd(X[1], X[3]));
+                    if (zho) caxpy(v, w2, cadd(X[0], X[4]));
+                    if (RESID) v = csub(b[(size_t)J * Lc.nx + I], v);
+                }
+                vc[(size_t)J * Lc.nx + I] = v;
+            }
+        }
     }
-    __syncthreads();
-    const int c = threadIdx.x % ZT_CX, rl = threadIdx.x / ZT_CX;
-    const int I = I0 + c, J = J0 + rl;
-    if (I >= Lc.nx || J >= Lc.ny) return;
-    cd v = czero();
-    if (unknown(Lc, I, J)) {
-        const int bb = 2 * rl + 2;
-        v = cscal(w0, sx[bb][c]);
-        caxpy(v, w1, cadd(sx[bb - 1][c], sx[bb + 1][c]));
-        if (zho) caxpy(v, w2, cadd(sx[bb - 2][c], sx[bb + 2][c]));
-        if (RESID) v = csub(b[(size_t)J * Lc.nx + I], v);
-    }
-    vc[(size_t)J * Lc.nx + I] = v;
 }
 
 hipError_t launch_zt(const Lev &Lf, const Lev &Lc, int zho, const cd *vf, const cd *b, cd *vc,
                      hipStream_t st, Batch bt)
 {
-    const int tx = cdiv(Lc.nx, ZT_CX), ty = cdiv(Lc.ny, ZT_CY);
+    const int tx = cdiv(Lc.nx, ZS_CX), ty = cdiv(Lc.ny, 4 * ZS_RPW);
     const dim3 g(tx * ty, bt.B);
     if (b)
         k_zt<true><<<g, 256, 0, st>>>(Lf, Lc, zho, vf, b, vc, tx, bt);
@@ -1485,9 +1556,23 @@ hipError_t launch_glk(const Lev &Lf, const Lev &Lc, int zho, const cd *x, const 
 }
 
 // ------------------------------------------------------------------------
-// Deflated residual t = v - A_h (Z v2), with Z v2 staged in LDS (66 x 18) and
-// never written to memory.
+// Deflated residual t = v - A_h (Z v2); Z v2 is formed in registers and never
+// written to memory.
+// A wave streams 64 consecutive fine columns i = c0 + lane (c0 even) and
+// writes the 58 of lanes 2..59 on DR_RPW rows.  Lane l loads v2 at coarse
+// column i >> 1 of every coarse row the strip needs; the Z rule's x part then
+// takes its coarse neighbours from the adjacent lanes (DPP shifts: an even
+// column i = 2I needs I - 1 from lane l - 1 and I + 1 from lane l + 2, an odd
+// one (i + 1) / 2 from lane l + 1), its y part combines the x-filtered coarse
+// rows, and the 5-point operator takes the west/east values of Z v2 from the
+// adjacent lanes and north/south from the rows before and after.  Coarse
+// values outside the grid or not unknowns count as 0, and so does Z v2 at a
+// fine node that is not an unknown.  A block is 4 waves stacked over
+// 4 * DR_RPW rows; every load is issued before the arithmetic.
 // ------------------------------------------------------------------------
+constexpr int DR_TX = 58, DR_RPW = 16, DR_NC = DR_RPW / 2 + 3;
+
+template <bool VARK>
 __global__ __launch_bounds__(256) void k_dresid(Lev Lf, Lev Lc, int zho,
                                                 const cd *__restrict__ v,
                                                 const cd *__restrict__ v2, cd *__restrict__ tout,
@@ -1500,51 +1585,104 @@ __global__ __launch_bounds__(256) void k_dresid(Lev Lf, Lev Lc, int zho,
         tout += blockIdx.y * nf;
         v2 += blockIdx.y * nc;
     }
-    __shared__ cd sz[VU_H][VU_W];
+    const int lane = threadIdx.x & 63;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int i0 = (t % tiles_x) * VU_TX, j0 = (t / tiles_x) * VU_TY;
+    const int i = (t % tiles_x) * DR_TX - 2 + lane;
+    const int j0 = (t / tiles_x) * (4 * DR_RPW) + (threadIdx.x >> 6) * DR_RPW;  // even
+    const int nx = Lf.nx, ny = Lf.ny;
+    if (j0 >= ny) return;  // the whole wave: no row here
+    const bool colin = i >= 0 && i < nx;
+    const int ic = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+    const bool outc = lane >= 2 && lane <= DR_TX + 1 && colin;
+    // coarse rows Jb .. Jb + DR_NC - 1 cover fine rows j0 - 1 .. j0 + DR_RPW
+    const int Jb = j0 / 2 - 1;
+    const int Iv = i >= 0 ? i >> 1 : -1;
+    const bool cin = Iv >= 0 && Iv < Lc.nx;
+    const int Ivc = Iv < 0 ? 0 : (Iv >= Lc.nx ? Lc.nx - 1 : Iv);
+    cd cr[DR_NC], vr[DR_RPW];
+    double kr[VARK ? DR_RPW : 1];
 #pragma unroll
-    for (int kq = 0; kq < (VU_W * VU_H + 255) / 256; kq++) {
-        const int q = threadIdx.x + 256 * kq;
-        if (q >= VU_W * VU_H) continue;
-        const int a = q % VU_W, bb = q / VU_W;
-        const int fi = i0 - 1 + a, fj = j0 - 1 + bb;
-        cd z = czero();
-        if (fi >= 0 && fi < Lf.nx && fj >= 0 && fj < Lf.ny && unknown(Lf, fi, fj))
-            z = prolong_at(Lc, v2, fi, fj, zho);
-        sz[bb][a] = z;
+    for (int q = 0; q < DR_NC; q++) {
+        const int J = Jb + q;
+        cr[q] = v2[(size_t)(J < 0 ? 0 : (J >= Lc.ny ? Lc.ny - 1 : J)) * Lc.nx + Ivc];
     }
-    __syncthreads();
-    const int i = i0 + (threadIdx.x & 63);
-    if (i >= Lf.nx) return;
-    const cd one = make_double2(1.0, 0.0);
 #pragma unroll
-    for (int rr = 0; rr < VU_TY / 4; rr++) {
-        const int jl = (threadIdx.x >> 6) * (VU_TY / 4) + rr;
-        const int j = j0 + jl;
-        if (j >= Lf.ny) break;
-        const int a = i - i0 + 1, bb = jl + 1;
-        const size_t p = (size_t)j * Lf.nx + i;
-        cd ap;
-        double aw, ae, as, an;
-        cd o = czero();
-        if (coef5(Lf, one, i, j, ap, aw, ae, as, an)) {
-            cd m = cmul(ap, sz[bb][a]);
-            caxpy(m, aw, sz[bb][a - 1]);
-            caxpy(m, ae, sz[bb][a + 1]);
-            caxpy(m, as, sz[bb - 1][a]);
-            caxpy(m, an, sz[bb + 1][a]);
-            o = csub(v[p], m);
+    for (int r = 0; r < DR_RPW; r++) {
+        const int j = j0 + r;
+        const size_t p = (size_t)(j < ny ? j : ny - 1) * nx + ic;
+        vr[r] = v[p];
+        if (VARK) kr[r] = Lf.k[p];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // x part of the Z rule on every coarse row (in place)
+    const double w0 = zho ? 0.75 : 1.0, w2 = zho ? 0.125 : 0.0;
+#pragma unroll
+    for (int q = 0; q < DR_NC; q++) {
+        const int J = Jb + q;
+        const double m = cin && J >= 0 && J < Lc.ny && unknown(Lc, Ivc, J) ? 1.0 : 0.0;
+        const cd c = cscal(m, cr[q]);
+        const cd cw = lane_from(c, true), ce = lane_from(c, false);
+        const cd ce2 = lane_from(ce, false);
+        // even i: w0 v(I) + w2 (v(I-1) + v(I+1)); odd i: (v(I) + v(I+1)) / 2
+        cd xe = cscal(w0, c);
+        caxpy(xe, w2, cadd(cw, ce2));
+        cr[q] = (i & 1) ? cscal(0.5, cadd(c, ce)) : xe;
+    }
+    // Z v2 on fine row j0 + rr, -1 <= rr <= DR_RPW (rr is a compile-time
+    // constant in the unrolled loop; j0 is even): coarse row j0 / 2 + rr / 2
+    // is cr[rr / 2 + 1] for even rr, and an odd rr lies between cr[(rr+1)/2]
+    // and the next one
+    auto zrow = [&](int rr) -> cd {
+        cd z;
+        if (rr & 1) {
+            const int q = (rr + 1) / 2;
+            z = cscal(0.5, cadd(cr[q], cr[q + 1]));
+        } else {
+            const int q = rr / 2 + 1;
+            z = cscal(w0, cr[q]);
+            caxpy(z, w2, cadd(cr[q - 1], cr[q + 1]));
         }
-        tout[p] = o;
+        const int j = j0 + rr;
+        const double m = colin && j >= 0 && j < ny && unknown(Lf, ic, j) ? 1.0 : 0.0;
+        return cscal(m, z);
+    };
+    const cd one = make_double2(1.0, 0.0);
+    cd zs = zrow(-1);
+    cd zc = zrow(0);
+#pragma unroll
+    for (int r = 0; r < DR_RPW; r++) {
+        const int j = j0 + r;
+        const cd zn = zrow(r + 1);
+        const cd zw = lane_from(zc, true), ze = lane_from(zc, false);
+        if (outc && j < ny) {
+            cd ap;
+            double aw, ae, as, an;
+            cd o = czero();
+            const double kv = VARK ? kr[r] : Lf.kc;
+            if (coef5k(Lf, one, i, j, kv, ap, aw, ae, as, an)) {
+                cd m = cmul(ap, zc);
+                caxpy(m, aw, zw);
+                caxpy(m, ae, ze);
+                caxpy(m, as, zs);
+                caxpy(m, an, zn);
+                o = csub(vr[r], m);
+            }
+            tout[(size_t)j * nx + i] = o;
+        }
+        zs = zc;
+        zc = zn;
     }
 }
 
 hipError_t launch_dresid(const Lev &Lf, const Lev &Lc, int zho, const cd *v, const cd *v2,
                          cd *t, hipStream_t st, Batch bt)
 {
-    const int tx = cdiv(Lf.nx, VU_TX), ty = cdiv(Lf.ny, VU_TY);
-    k_dresid<<<dim3(tx * ty, bt.B), 256, 0, st>>>(Lf, Lc, zho, v, v2, t, tx, bt);
+    const int tx = cdiv(Lf.nx, DR_TX), ty = cdiv(Lf.ny, 4 * DR_RPW);
+    const dim3 g(tx * ty, bt.B);
+    if (Lf.k)
+        k_dresid<true><<<g, 256, 0, st>>>(Lf, Lc, zho, v, v2, t, tx, bt);
+    else
+        k_dresid<false><<<g, 256, 0, st>>>(Lf, Lc, zho, v, v2, t, tx, bt);
     HD_LAUNCH_CHECK();
 }
 
@@ -2126,9 +2264,14 @@ __device__ __forceinline__ cd ldc(const cf *p)
     return make_double2(v.x, v.y);
 }
 // Store v; return the value as stored (rounded to complex64 for cf).
+// (complex128 entries are stored non-temporally: the updated vector is the
+// new basis vector, streamed past the caches like the rest of the basis)
 __device__ __forceinline__ cd stc(cd *p, cd v)
 {
-    *p = v;
+    d2v t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, (d2v *)p);
     return v;
 }
 __device__ __forceinline__ cd stc(cf *p, cd v)
@@ -2452,7 +2595,7 @@ hipError_t launch_mupdate32(cf *w, const cf *V, size_t ld, int m, const cd *c, s
 // norm) into sig_out[0].  cond: second-pass reduction, which stores zeros
 // unless need_reorth(cond, jcond).
 __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int nblk,
-                                                cd *__restrict__ out, int mode,
+                                                cd *out, int mode,
                                                 const cd *__restrict__ cond, int jcond,
                                                 const cd *__restrict__ sig, int nsig,
                                                 cd *__restrict__ sig_out, Batch bt,
@@ -2496,7 +2639,8 @@ __global__ __launch_bounds__(256) void k_reduce(const cd *__restrict__ part, int
     }
     if (pub_dst) {
         // publish pub_src[0, pub_n) (written by earlier kernels, and out[i]
-        // just above) to host-visible memory
+        // just above: out may lie inside pub_src, so neither is restrict) to
+        // host-visible memory
         __syncthreads();
         for (int q = threadIdx.x; q < pub_n; q += 256) pub_dst[q] = pub_src[q];
         __threadfence_system();

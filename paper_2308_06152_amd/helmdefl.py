@@ -58,7 +58,9 @@ class Opts(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters_total", ctypes.c_int),
                 ("inner_iters_max", ctypes.c_int), ("converged", ctypes.c_int),
-                ("relres", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+                ("relres", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double), ("t_coarse_ms", ctypes.c_double),
+                ("t_vcycle_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -120,10 +120,10 @@ def test_batched_solve_can_be_switched_off(H, ora):
 
 
 @pytest.mark.parametrize("kw", [dict(outer=1), dict(outer=2, coarse_mode=1, coarse_iters=20),
-                                dict(precision=1)],
-                         ids=["gcr", "left_gmres", "mixed"])
+                                dict(precision=2)],
+                         ids=["gcr", "left_gmres", "mixed_c64basis"])
 def test_multi_rhs_paths_without_batching(H, ora, kw):
-    """GCR, left GMRES and the mixed-precision option solve several right-hand
+    """GCR, left GMRES and the complex64-basis option solve several right-hand
     sides one after another: each equals its single solve bit for bit."""
     n, k = 65, 15.0
     nx, ny, hx, hy = inputs.unit_square(n)
@@ -138,3 +138,56 @@ def test_multi_rhs_paths_without_batching(H, ora, kw):
         assert ib[q]["outer_iters"] == iq[0]["outer_iters"]
         assert torch.equal(xb[q], xs)
         assert ib[q]["converged"]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_batched_mixed_vcycle(H, ora, case):
+    """Batched complex64 fine-grid V-cycle (PREC_MIXED): the same FP32 kernels
+    per right-hand side as the single mixed cycle (bit for bit), and within
+    the FP32 bar of the FP64 oracle applied to the FP32-rounded input."""
+    S, P = make_pair(H, ora, case, precision=1)
+    B = 3
+    r = np.stack([inputs.random_complex((P.ny, P.nx), 170 + q) for q in range(B)])
+    r = r.astype(np.complex64).astype(np.complex128)
+    zb = host(S.vcycle(dev(r)))
+    for q in range(B):
+        assert np.array_equal(zb[q], host(S.vcycle(dev(r[q]))))
+        assert rel(zb[q], ora.vcycle(P, r[q])) <= 1e-5
+
+
+def test_batched_mixed_solves(H, ora):
+    """Batched FGMRES with the complex64 fine-grid V-cycle: every right-hand
+    side converges to the FP64 tolerance (true residual from the oracle
+    operator), within one outer iteration of the FP64 oracle's solve, and its
+    solution matches the oracle's at an equal forced iteration count to the
+    FP32 level."""
+    w = inputs.wedge(145, 241)
+    kf = w.kfield()
+    okw = dict(coarse_op=w.coarse_op, coarse_mode=2, coarse_tol=w.coarse_tol,
+               coarse_iters=w.coarse_maxit, coarse_restart=w.coarse_restart, restart=w.restart,
+               tol=w.tol)
+    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, k=dev(kf), precision=1, **okw)
+    P = ora.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, k=kf, coarse_op=w.coarse_op,
+                    coarsest_nodes=S.opts.coarsest_nodes, coarse_mode=ora.CMODE_TOL,
+                    coarse_tol=w.coarse_tol, coarse_iters=w.coarse_maxit,
+                    coarse_restart=w.coarse_restart)
+    srcs = np.stack([inputs.point_source(w.nx, w.ny, w.hx, w.hy, i, w.ny - 6)
+                     for i in (20, 72, 130)])
+    xb, ib = S.solve(dev(srcs))
+    xb = host(xb)
+    for q in range(len(srcs)):
+        xo, io = ora.fgmres(P, srcs[q], restart=w.restart, tol=w.tol, maxit=200)
+        assert ib[q]["converged"] and io.converged
+        assert abs(ib[q]["outer_iters"] - io.iters) <= 1
+        r = ora.helm_apply(P, xb[q]) - srcs[q]
+        assert np.linalg.norm(r) / np.linalg.norm(srcs[q]) <= 1e-6
+    # equal forced outer count, fixed inner count
+    Sf = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, k=dev(kf), precision=1,
+                  **dict(okw, coarse_mode=1, coarse_iters=10, force_iters=5))
+    Pf = P.replace(coarse_mode=ora.CMODE_FIXED, coarse_iters=10)
+    xf, inf = Sf.solve(dev(srcs))
+    xf = host(xf)
+    for q in range(len(srcs)):
+        xo, io = ora.fgmres(Pf, srcs[q], restart=w.restart, tol=w.tol, maxit=200, force_iters=5)
+        assert inf[q]["outer_iters"] == io.iters == 5
+        assert rel(xf[q], xo) <= 1e-5

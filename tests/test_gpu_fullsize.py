@@ -1,9 +1,11 @@
 """Parity at the benchmark's full size, in the configuration bench.py times:
 the 4097^2, k = 800 Sommerfeld workload with ReD-Glk2.  The oracle (on the
 GPU host's CPU) computes whole-grid operators at this size in seconds; the
-deflation step is compared with a fixed number of inner iterations, and the
-full solve by properties (convergence, and the true residual recomputed by the
-oracle's operator).  The batched layered workload is checked the same way."""
+deflation step and the FGMRES iterates are compared with fixed numbers of
+inner and outer iterations, and the full solve by properties (convergence,
+and the true residual recomputed by the oracle's operator); a whole oracle
+solve at this size (about 2000 inner iterations) takes too long for a test.
+The batched layered workload is checked the same way."""
 import numpy as np
 import pytest
 
@@ -53,6 +55,31 @@ def test_full_size_adef1_fixed_inner(H, ora):
     want, it = ora.deflate_apply(P, v, ora.DEFL_ADEF1)
     assert it == 3
     assert rel(got, want) <= 1e-11
+
+
+def test_full_size_solve_equal_iterations(H, ora):
+    """The benchmark's FGMRES at full size against the oracle's at an equal,
+    forced count: two outer iterations, each with a coarse solve of exactly
+    three inner iterations (the oracle then finishes in seconds).  The
+    iterates must agree to the per-solve bar of 1e-5 (they agree to rounding:
+    every step is the same linear algebra)."""
+    w = inputs.large_plain()
+    S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+                 coarse_mode=H.CMODE_FIXED, coarse_iters=3, coarse_restart=w.coarse_restart,
+                 restart=4, tol=w.tol, force_iters=2)
+    P = ora.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, kconst=w.kconst, coarse_op=w.coarse_op,
+                    coarsest_nodes=S.opts.coarsest_nodes, coarse_mode=ora.CMODE_FIXED,
+                    coarse_iters=3, coarse_restart=w.coarse_restart)
+    b = w.rhs()
+    x, info = S.solve(dev(b))
+    # (restart 4 keeps the oracle's bases to a few GB; two iterations never restart)
+    xo, io = ora.fgmres(P, b, restart=4, tol=w.tol, maxit=10, force_iters=2)
+    assert info[0]["outer_iters"] == io.iters == 2
+    d = rel(host(x), xo)
+    print(f"4097^2 forced 2 outer / 3 inner: ||x - x_oracle|| / ||x_oracle|| = {d:.3e}, "
+          f"relres GPU {info[0]['relres']:.6e} oracle {io.relres:.6e}")
+    assert d <= 1e-5
+    assert abs(info[0]["relres"] - io.relres) <= 1e-6 * io.relres
 
 
 def test_full_size_solve_properties(H, ora, large):

@@ -55,3 +55,39 @@ def test_graph_solve_matches_direct(H, ora, precision):
         assert ig[0]["inner_iters_total"] == idd[0]["inner_iters_total"]
         assert ig[0]["converged"] and ig[0]["relres"] <= 1e-6
         assert np.array_equal(host(xg), host(xd)), rep
+
+
+@pytest.mark.parametrize("case", GCASES[:3], ids=[c[0] for c in GCASES[:3]])
+def test_batched_graph_chunks_match_direct(H, ora, case):
+    """Batched solves with the coarse GMRES steps replayed in captured chunks
+    against direct launches: right-hand sides that converge at different
+    inner and outer iterations (the chunks run on past a convergence, and a
+    new active mask reaches later chunks), three replays with eager work and
+    synchronisations in between, each bit for bit equal to the direct solve."""
+    kw = dict(coarse_mode=2, coarse_tol=0.1, coarse_iters=300, coarse_restart=11, restart=30)
+    Sg, P = make_pair(H, ora, case, graphs=1, **kw)
+    Sd, _ = make_pair(H, ora, case, graphs=0, **kw)
+    nx, ny = P.nx, P.ny
+    b = np.stack([inputs.point_source(nx, ny, P.hx, P.hy, nx // 2, ny // 2),
+                  inputs.random_complex((ny, nx), 215),
+                  inputs.point_source(nx, ny, P.hx, P.hy, 3, ny // 3),
+                  np.zeros((ny, nx), complex)])
+    xd, idd = Sd.solve(dev(b))
+    xd = host(xd)
+    assert len({i["inner_iters_total"] for i in idd[:3]}) > 1
+    for rep in range(3):
+        xg, ig = Sg.solve(dev(b))
+        for q in range(len(b)):
+            assert ig[q]["outer_iters"] == idd[q]["outer_iters"]
+            assert ig[q]["inner_iters_total"] == idd[q]["inner_iters_total"]
+        assert np.array_equal(host(xg), xd), rep
+        # eager work and a synchronisation between replays
+        Sg.apply(dev(b[1]))
+        torch.cuda.synchronize()
+    # batched deflation with a fixed inner count, replayed
+    Sgf, _ = make_pair(H, ora, case, graphs=1, coarse_mode=1, coarse_iters=9, coarse_restart=4)
+    Sdf, _ = make_pair(H, ora, case, graphs=0, coarse_mode=1, coarse_iters=9, coarse_restart=4)
+    v = np.stack([inputs.random_complex((ny, nx), 216 + q) for q in range(3)])
+    want = host(Sdf.deflate(dev(v), 2))
+    for rep in range(2):
+        assert np.array_equal(host(Sgf.deflate(dev(v), 2)), want), rep

@@ -25,7 +25,7 @@ TCASES = [
     (("som257_k40_c1089", 257, 257, 1, "const", 40.0, 1), 1089),  # 2 fused levels
     (("som161_vark", 161, 161, 1, "var", (20.0, 60.0), 1), 0),  # variable k
     (("som97x161", 97, 161, 1, "const", 30.0, 0), 0),           # rectangular
-    (("dir37x53_vark", 37, 53, 0, "var", (5.0, 25.0), 0), 0),   # ragged small
+    (("dir65x97_vark", 65, 97, 0, "var", (5.0, 25.0), 0), 0),   # ragged, Dirichlet, var k
 ]
 
 
@@ -53,6 +53,27 @@ def test_vcycle_fused_tail_matches_per_level(H, ora, case, coarsest):
     want = host(Sl.vcycle(dev(r)))
     for rep in range(2):
         same(host(Sf.vcycle(dev(r))), want, case, 1e-14)
+
+
+@pytest.mark.parametrize("case,coarsest", TCASES, ids=[c[0][0] for c in TCASES])
+def test_fused_tails_run(H, ora, case, coarsest):
+    """The fused kernels really run for every case above: a cycle launches
+    fewer downward and upward passes with the tails on (the timing hooks file
+    a fused tail as one launch)."""
+    Sf, Sl, P = _pair(H, ora, case, coarsest)
+    r = dev(inputs.random_complex((P.ny, P.nx), 304))
+    counts = {}
+    for name, S in (("fused", Sf), ("per_level", Sl)):
+        for kc in (H.K_VC_DOWN, H.K_VC_UP):
+            S.timing_enable(kc, -1)
+            S.vcycle(r)
+            counts[name, kc] = S.timing_read()[0]
+            S.timing_enable(-1, -1)
+    nlev = Sl.num_levels()
+    assert counts["per_level", H.K_VC_DOWN] == nlev - 1
+    assert counts["per_level", H.K_VC_UP] == nlev - 1
+    assert counts["fused", H.K_VC_DOWN] < nlev - 1
+    assert counts["fused", H.K_VC_UP] < nlev - 1
 
 
 @pytest.mark.parametrize("limit", [1, 100, 4225, 20000])
