@@ -283,9 +283,13 @@ def layered_multi_bench(a, torch, H, inputs, prec):
     def step(precision, keep=False):
         infos, xs = [], []
         for w, kf, b in zip(ws, kfs, bs):
+            t = time.perf_counter()
             S = H.Solver(w.nx, w.ny, w.hx, w.hy, w.bc, k=kf, precision=precision, **opts(w))
             x, info = S.solve(b)
             S.close()
+            # progress on stderr (the solve has synchronised already)
+            print(f"bench.py: {w.freq:g} Hz, {len(info)} sources, precision {precision}: "
+                  f"{time.perf_counter() - t:.2f} s", file=sys.stderr, flush=True)
             infos.append(info)
             if keep:
                 xs.append(x)

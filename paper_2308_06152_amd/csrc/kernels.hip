@@ -12,12 +12,7 @@
 //    XCDs, so tiles are renumbered to give every XCD a contiguous band of the
 //    grid, keeping vertical halos in that XCD's L2;
 //  * reductions are deterministic: fixed per-block partial sums, then a fixed
-//    tree in a second kernel;
-//  * no implicit contraction of a multiply and an add into an FMA: every FMA
-//    is written out, so an expression gives the same bits in every kernel
-//    that evaluates it (the fused V-cycle tails and the per-level passes, the
-//    batched and the single kernels), whatever the instruction scheduling.
-#pragma clang fp contract(off)
+//    tree in a second kernel.
 #include "hd_common.h"
 
 #include <type_traits>
