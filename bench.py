@@ -91,9 +91,10 @@ def kernels_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, coarse_restart):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None if
-    absent or taken on a different version of the kernels."""
+    absent, taken on a different version of the kernels or with another coarse
+    restart (which sets the average number of basis vectors per launch)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -101,6 +102,8 @@ def measured_traffic(kernel, workload):
         return None
     e = t.get(f"{kernel}@{workload}")
     if not e or e.get("kernels_sha") != kernels_hash():
+        return None
+    if e.get("coarse_restart", coarse_restart) != coarse_restart:
         return None
     return e.get("bytes_per_launch")
 
@@ -426,7 +429,8 @@ def main():
         print("bench.py: a solve did not converge", file=sys.stderr)
         sys.exit(1)
     achieved = (k_bytes / 1e9) / (k_ms / 1e3) if k_ms > 0 else 0.0
-    traffic = measured_traffic(a.roofline_kernel, w.name) if prec == H.PREC_FP64 else None
+    traffic = (measured_traffic(a.roofline_kernel, w.name, opts["coarse_restart"])
+               if prec == H.PREC_FP64 and nrhs == 1 else None)
     mixed = prec != H.PREC_FP64
     wname = w.name + {H.PREC_FP64: "", H.PREC_MIXED: "_mixed",
                       H.PREC_MIXED_C64BASIS: "_mixed_c64basis"}[prec]
