@@ -259,9 +259,6 @@ hipError_t launch_scale(const cd *w, const cd *nrm, cd *v, size_t n, hipStream_t
 hipError_t launch_lincomb(const cd *V, size_t ld, int m, const cd *y, cd *out, size_t n,
                           int accumulate, hipStream_t st, Batch bt = Batch{}, size_t vbs = 0,
                           size_t obs = 0);
-// out (+)= sum_i y_i V_i for a complex64 basis (FP64 sums).
-hipError_t launch_lincomb32(const cf *V, size_t ld, int m, const cd *y, cd *out, size_t n,
-                            int accumulate, hipStream_t st);
 // p[0..n) = 0.
 hipError_t launch_zero(cd *p, size_t n, hipStream_t st);
 // out = in with the non-unknown (Dirichlet boundary) entries set to zero.

@@ -151,7 +151,7 @@ struct BatchWS {
     cd *lr[MAXLEV] = {}, *lx[MAXLEV] = {};
     cf *lrf[MAXLEV] = {}, *lxf[MAXLEV] = {};  // complex64 levels (mixed precision)
     cd *v1 = nullptr, *v2 = nullptr, *tf = nullptr;
-    cd *Vc = nullptr, *wc = nullptr, *zc = nullptr;
+    cd *Vc = nullptr, *Zc = nullptr;  // inner basis V and Z = M^-1 V (slot-major, B per slot)
     cd *part = nullptr, *partn = nullptr;
     cd *hbuf = nullptr, *sig = nullptr, *ydev = nullptr;
     cd *V = nullptr, *Z = nullptr, *w = nullptr, *bm = nullptr;  // outer FGMRES
@@ -187,9 +187,9 @@ struct helm_ctx {
 
     // deflation workspace (coarse grid = level 1)
     cd *v1 = nullptr, *v2 = nullptr, *tf = nullptr;
-    // inner GMRES
+    // inner GMRES: basis V (mc + 1 vectors) and Z (mc vectors), z_j = M^-1 v_j
     int mc = 0;
-    cd *Vc = nullptr, *wc = nullptr, *zc_ = nullptr, *xin = nullptr;
+    cd *Vc = nullptr, *Zc = nullptr, *xin = nullptr;
     // mixed precision: the inner basis in complex64 (FP64 A_2h output in wtmp)
     bool basis32 = false;
     cf *Vc32 = nullptr;
@@ -709,8 +709,9 @@ int coarse_apply(helm_ctx *h, const cd *x, const cd *b, cd *y)
 int inner_step_enqueue(helm_ctx *h, int j, int slot, bool readback = true)
 {
     const size_t nc = h->L[1].n();
-    RCHK(vcycle(h, 1, h->Vc + (size_t)j * nc, h->zc_, 0, nullptr, h->sig + j));
-    RCHK(coarse_apply(h, h->zc_, nullptr, h->Vc + (size_t)(j + 1) * nc));
+    cd *z = h->Zc + (size_t)j * nc;
+    RCHK(vcycle(h, 1, h->Vc + (size_t)j * nc, z, 0, nullptr, h->sig + j));
+    RCHK(coarse_apply(h, z, nullptr, h->Vc + (size_t)(j + 1) * nc));
     return arnoldi_lazy_enqueue(h, h->Vc, nc, j + 1, nc, 1, slot, readback);
 }
 
@@ -746,8 +747,9 @@ int arnoldi_lazy_enqueue32(helm_ctx *h, size_t n, int j1, int slot, bool readbac
 int inner_step_enqueue32(helm_ctx *h, int j, int slot, bool readback = true)
 {
     const size_t nc = h->L[1].n();
-    RCHK(vcycle32(h, h->Vc32 + (size_t)j * nc, h->zc_, h->sig + j));
-    RCHK(coarse_apply(h, h->zc_, nullptr, h->wtmp));
+    cd *z = h->Zc + (size_t)j * nc;
+    RCHK(vcycle32(h, h->Vc32 + (size_t)j * nc, z, h->sig + j));
+    RCHK(coarse_apply(h, z, nullptr, h->wtmp));
     return arnoldi_lazy_enqueue32(h, nc, j + 1, slot, readback);
 }
 
@@ -806,8 +808,12 @@ int basis32_set0(helm_ctx *h, const cd *u)
 // The host needs each step's Hessenberg column only to test convergence, so
 // step j+1 is enqueued before the host waits for step j: the GPU never idles
 // on the read-back.  A converged cycle leaves one speculative step, whose
-// results are not used.  With the mixed-precision option the basis is stored
-// in complex64 (everything else, and all arithmetic, stays FP64).
+// results are not used.  Each step keeps z_j = M^-1 v_j (the V-cycle output
+// that A_2h is applied to), so the end of a cycle adds sum_i y_i z_i to x
+// without another V-cycle: with an exact coarsest solve the V-cycle is a fixed
+// linear operator, and this equals M^-1 (V y) up to rounding.  With the
+// complex64-basis option V is stored in complex64 (Z, and all arithmetic,
+// stay FP64).
 int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
 {
     const size_t nc = h->L[1].n();
@@ -825,7 +831,6 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
     if (bnorm == 0.0) return HELM_OK;
     Givens gv(m);
     std::vector<zc> col(m + 1), y;
-    std::vector<double> unorm(m + 1);
     bool first = true;
     for (;;) {
         double beta;
@@ -844,7 +849,6 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
         if (!fixed && beta <= tol * bnorm) break;
         if (it >= cap || beta == 0.0) break;
         gv.start(beta);
-        unorm[0] = beta;
         const int steps = std::min(m, cap - it);
         int jend = 0;
         bool stop = false;
@@ -857,20 +861,15 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
             const double res = gv.add_column(j, col.data(), hn);
             it++;
             jend = j + 1;
-            unorm[j + 1] = hn;
             if ((!fixed && res <= tol * bnorm) || hn == 0.0) {
                 stop = true;
                 break;
             }
         }
+        // x += sum_i y_i M^-1 v_i, from the z_i the steps kept
         gv.solve(jend, y);
-        for (int i = 0; i < jend; i++) y[i] /= unorm[i];  // v_i = u_i / ||u_i||
         RCHK(upload_y(h, y));
-        if (b32)
-            HCHK(launch_lincomb32(h->Vc32, nc, jend, h->ydev, h->wc, nc, 0, h->st));
-        else
-            HCHK(launch_lincomb(h->Vc, nc, jend, h->ydev, h->wc, nc, 0, h->st));
-        RCHK(vcycle(h, 1, h->wc, x, 1, nullptr));
+        HCHK(launch_lincomb(h->Zc, nc, jend, h->ydev, x, nc, 1, h->st));
         if (it >= cap) break;
         if (stop && fixed) break;
         first = false;
@@ -1215,7 +1214,7 @@ void free_batch(BatchWS *W)
         dfree(W->lxf[l]);
     }
     for (void *p : {(void *)W->v1, (void *)W->v2, (void *)W->tf,
-                    (void *)W->Vc, (void *)W->wc, (void *)W->zc, (void *)W->part,
+                    (void *)W->Vc, (void *)W->Zc, (void *)W->part,
                     (void *)W->partn, (void *)W->hbuf, (void *)W->sig, (void *)W->ydev,
                     (void *)W->V, (void *)W->Z, (void *)W->w, (void *)W->bm, (void *)W->dmask})
         dfree(p);
@@ -1256,8 +1255,11 @@ int ensure_batch(helm_ctx *h, int B, bool outer)
         if (!rc) rc = dalloc(&W->v2, b * nc);
         if (!rc) rc = dalloc(&W->tf, b * nf);
         if (!rc) rc = dalloc(&W->Vc, (size_t)(h->mc + 1) * b * nc);
-        if (!rc) rc = dalloc(&W->wc, b * nc);
-        if (!rc) rc = dalloc(&W->zc, b * nc);
+        if (!rc) rc = dalloc(&W->Zc, (size_t)h->mc * b * nc);
+        // slots past a right-hand side's last step are read with weight 0
+        // at the end of a cycle: keep them finite
+        if (!rc && hipMemset(W->Zc, 0, (size_t)h->mc * b * nc * sizeof(cd)) != hipSuccess)
+            rc = HELM_EHIP;
         if (!rc) rc = dalloc(&W->part, b * krylov_blocks_max(nf) * PSTRIDE);
         if (!rc) rc = dalloc(&W->partn, b * krylov_blocks_max(nf) * PSTRIDE);
         if (!rc) rc = dalloc(&W->hbuf, b * SB);
@@ -1485,8 +1487,9 @@ int inner_step_b(helm_ctx *h, int j, int slot, const int *dm, int nact)
 {
     BatchWS *W = h->bw;
     const size_t ld = (size_t)W->B * h->L[1].n();
-    RCHK(vcycle_b(h, 1, W->Vc + (size_t)j * ld, W->zc, 0, nullptr, W->sig + j, dm));
-    RCHK(coarse_apply_b(h, W->zc, nullptr, W->Vc + (size_t)(j + 1) * ld, dm));
+    cd *z = W->Zc + (size_t)j * ld;
+    RCHK(vcycle_b(h, 1, W->Vc + (size_t)j * ld, z, 0, nullptr, W->sig + j, dm));
+    RCHK(coarse_apply_b(h, z, nullptr, W->Vc + (size_t)(j + 1) * ld, dm));
     return arnoldi_lazy_b(h, j + 1, slot, dm, nact);
 }
 
@@ -1589,7 +1592,6 @@ int coarse_solve_b(helm_ctx *h, const cd *bvec, cd *x, const std::vector<char> &
         if (bn[b] == 0.0) live[b] = 0;
     }
     std::vector<Givens> gv(B, Givens(m));
-    std::vector<std::vector<double>> unorm(B, std::vector<double>(m + 1));
     std::vector<std::vector<zc>> y(B);
     std::vector<int> jend(B);
     std::vector<char> stop(B), cyc(B), stepm(B);
@@ -1625,7 +1627,6 @@ int coarse_solve_b(helm_ctx *h, const cd *bvec, cd *x, const std::vector<char> &
             jend[b] = 0;
             if (!cyc[b]) continue;
             gv[b].start(beta[b]);
-            unorm[b][0] = beta[b];
         }
         const int steps = std::min(m, cap - itmin);
         int nact = nlive;
@@ -1640,7 +1641,6 @@ int coarse_solve_b(helm_ctx *h, const cd *bvec, cd *x, const std::vector<char> &
                 const double res = gv[b].add_column(j, col.data(), hn);
                 iters[b]++;
                 jend[b] = j + 1;
-                unorm[b][j + 1] = hn;
                 if ((!fixed && res <= tol * bn[b]) || hn == 0.0 || iters[b] >= cap) {
                     stop[b] = 1;
                     stepm[b] = 0;
@@ -1702,20 +1702,19 @@ int coarse_solve_b(helm_ctx *h, const cd *bvec, cd *x, const std::vector<char> &
                 }
             }
         }
-        // x += V-cycle(sum_i y_i v_i) for every right-hand side of the cycle
+        // x += sum_i y_i M^-1 v_i for every right-hand side of the cycle, from
+        // the z_i its steps kept (a shorter cycle's y is padded with zeros)
         int jmax = 0;
         for (int b = 0; b < B; b++) {
             y[b].clear();
             if (!cyc[b]) continue;
             gv[b].solve(jend[b], y[b]);
-            for (int i = 0; i < jend[b]; i++) y[b][i] /= unorm[b][i];
             jmax = std::max(jmax, jend[b]);
         }
         RCHK(upload_y_b(h, y, jmax));
         dm = upload_mask(h, cyc);
         MCHK(dm);
-        HCHK(launch_lincomb(W->Vc, ld, jmax, W->ydev, W->wc, n, 0, h->st, Batch{B, dm}, n, n));
-        RCHK(vcycle_b(h, 1, W->wc, x, 1, nullptr, nullptr, dm));
+        HCHK(launch_lincomb(W->Zc, ld, jmax, W->ydev, x, n, 1, h->st, Batch{B, dm}, n, n));
         for (int b = 0; b < B; b++)
             if (cyc[b] && ((fixed && stop[b]) || iters[b] >= cap)) live[b] = 0;
         first = false;
@@ -1993,8 +1992,7 @@ void release(helm_ctx *h)
     dfree(h->v2);
     dfree(h->tf);
     dfree(h->Vc);
-    dfree(h->wc);
-    dfree(h->zc_);
+    dfree(h->Zc);
     dfree(h->xin);
     dfree(h->Vc32);
     dfree(h->wtmp);
@@ -2139,8 +2137,7 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
     if (!rc) rc = dalloc(&h->v2, nc);
     if (!rc) rc = dalloc(&h->tf, nf);
     if (!rc) rc = dalloc(&h->Vc, (size_t)(h->mc + 1) * nc);
-    if (!rc) rc = dalloc(&h->wc, nc);
-    if (!rc) rc = dalloc(&h->zc_, nc);
+    if (!rc) rc = dalloc(&h->Zc, (size_t)h->mc * nc);
     if (!rc) rc = dalloc(&h->xin, nc);
     // with HELM_PREC_MIXED_C64BASIS the inner basis is complex64 (when the
     // inner V-cycle has a level below level 1)

@@ -2693,7 +2693,10 @@ __global__ __launch_bounds__(256) void k_lincomb(const TV *__restrict__ V, size_
     const size_t p = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     cd s = accumulate ? out[p] : czero();
-    for (int i = 0; i < m; i++) s = cadd(s, cmul(y[i], ldc(V + (size_t)i * ld + p)));
+    // a zero weight skips its vector: slots past a right-hand side's last
+    // step (padded with zeros) never enter the sum, whatever they hold
+    for (int i = 0; i < m; i++)
+        if (y[i].x != 0.0 || y[i].y != 0.0) s = cadd(s, cmul(y[i], ldc(V + (size_t)i * ld + p)));
     out[p] = s;
 }
 
@@ -2703,14 +2706,6 @@ hipError_t launch_lincomb(const cd *V, size_t ld, int m, const cd *y, cd *out, s
     k_lincomb<cd><<<dim3((unsigned)((n + 255) / 256), bt.B), 256, 0, st>>>(V, ld, m, y, out, n,
                                                                            accumulate, vbs, obs,
                                                                            bt);
-    HD_LAUNCH_CHECK();
-}
-
-hipError_t launch_lincomb32(const cf *V, size_t ld, int m, const cd *y, cd *out, size_t n,
-                            int accumulate, hipStream_t st)
-{
-    k_lincomb<cf><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(V, ld, m, y, out, n, accumulate,
-                                                               0, 0, Batch{});
     HD_LAUNCH_CHECK();
 }
 
