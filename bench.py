@@ -123,18 +123,20 @@ def host_cpu():
 
 
 def _oracle_problem(oracle, w, coarsest_nodes, **kw):
+    kw.setdefault("coarse_restart", w.coarse_restart)
     return oracle.Problem(w.nx, w.ny, w.hx, w.hy, bc=w.bc, k=w.kfield(), kconst=w.kconst,
-                          coarse_op=w.coarse_op, coarse_restart=w.coarse_restart,
-                          coarsest_nodes=coarsest_nodes, **kw)
+                          coarse_op=w.coarse_op, coarsest_nodes=coarsest_nodes, **kw)
 
 
-def cpu_baseline_full(w, coarsest_nodes, reps=5):
-    """Time whole oracle solves of the workload (small grids): the median of
-    `reps` solves with all host threads, and of 3 with one thread."""
+def cpu_baseline_full(w, coarsest_nodes, coarse_restart, reps=5):
+    """Time whole oracle solves of the workload (small grids), with the coarse
+    restart of the GPU run: the median of `reps` solves with all host threads,
+    and of 3 with one thread."""
     import oracle
     oracle.build(force=False)
     P = _oracle_problem(oracle, w, coarsest_nodes, coarse_mode=oracle.CMODE_TOL,
-                        coarse_tol=w.coarse_tol, coarse_iters=w.coarse_maxit)
+                        coarse_tol=w.coarse_tol, coarse_iters=w.coarse_maxit,
+                        coarse_restart=coarse_restart)
     b = w.rhs()
     model, nthr = host_cpu()
     res = {}
@@ -159,62 +161,60 @@ def cpu_baseline_full(w, coarsest_nodes, reps=5):
     }
 
 
-def cpu_baseline(w, info, coarsest_nodes):
+def cpu_baseline(w, info, coarsest_nodes, coarse_restart):
     """Time the oracle on a bounded sample of the workload and extrapolate.
 
-    Sample (C oracle, full grid, with all host threads and again with one):
-    one A_h apply, one coarse GMRES solve with 1 and with 8 fixed iterations
-    (their difference over 7 gives the cost of one inner iteration at the inner
-    steps j = 1..7, about the average step of a restart-15 cycle), and one
-    A-DEF1 application with a 1-iteration coarse solve (the fine-grid part of
-    an outer iteration).  Estimate of one solve = outer * (fine part +
-    coarse-solve overhead + A_h) + inner_total * (one inner iteration), with
-    the GPU run's counts; the outer Gram-Schmidt on the fine grid is left out
-    (it favours the CPU)."""
+    Sample (C oracle, full grid, coarse restart m of the GPU run, with all host
+    threads and again with one): one A_h apply; one coarse GMRES solve of m and
+    one of 2m fixed iterations, whose difference C is one whole inner cycle
+    (m steps, the cycle's solution update and the restart residual); one
+    A-DEF1 application with an m-iteration coarse solve (the fine-grid part of
+    an outer iteration plus one cycle).  Estimate of one solve =
+    outer * (A_h + A-DEF1 - C) + (inner_total / m) * C, with the GPU run's
+    counts; the outer Gram-Schmidt on the fine grid is left out (it favours
+    the CPU)."""
     import oracle
     from paper_2308_06152_amd import inputs
     oracle.build(force=False)
+    m = coarse_restart
     P = _oracle_problem(oracle, w, coarsest_nodes, coarse_mode=oracle.CMODE_FIXED,
-                        coarse_iters=1)
+                        coarse_iters=m, coarse_restart=m)
     nxc, nyc = oracle.coarse_dims(P)
     v = inputs.random_complex((w.ny, w.nx), 11)
     v1 = inputs.random_complex((nyc, nxc), 12)
     model, nthr = host_cpu()
 
+    def timed(f, *args):
+        t0 = time.perf_counter()
+        f(*args)
+        return time.perf_counter() - t0
+
     def sample():
-        t0 = time.perf_counter()
-        oracle.helm_apply(P, v)
-        t_a = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.coarse_solve(P, v1)
-        t_c1 = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.coarse_solve(P.replace(coarse_iters=8), v1)
-        t_c8 = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.deflate_apply(P, v, oracle.DEFL_ADEF1)
-        t_d1 = time.perf_counter() - t0
-        per_inner = max((t_c8 - t_c1) / 7.0, 0.0)
-        overhead = max(t_c1 - per_inner, 0.0)
-        fine = max(t_d1 - t_c1, 0.0)
-        est = (info["outer_iters"] * (fine + overhead + t_a)
-               + info["inner_iters_total"] * per_inner)
-        return est, (t_a, t_c1, t_c8, t_d1)
+        oracle.helm_apply(P, v)  # warm-up: thread start, first touch of the output
+        t_a = timed(oracle.helm_apply, P, v)
+        t_m = timed(oracle.coarse_solve, P, v1)
+        t_2m = timed(oracle.coarse_solve, P.replace(coarse_iters=2 * m), v1)
+        t_d = timed(oracle.deflate_apply, P, v, oracle.DEFL_ADEF1)
+        cycle = max(t_2m - t_m, 0.0)
+        est = (info["outer_iters"] * max(t_a + t_d - cycle, 0.0)
+               + info["inner_iters_total"] / m * cycle)
+        return est, (t_a, t_m, t_2m, t_d)
 
     res = {}
     for th in (nthr, 1):
         oracle.set_threads(th)
         res[th] = sample()
     oracle.set_threads(nthr)
-    est, (t_a, t_c1, t_c8, t_d1) = res[nthr]
+    est, (t_a, t_m, t_2m, t_d) = res[nthr]
     return {
         "value": 1.0 / est, "unit": "solves/s", "cores": nthr, "kind": "oracle",
-        "sample": (f"C oracle with {nthr} threads on the full {w.nx}x{w.ny} grid: A_h apply "
-                   f"{t_a:.2f}s, coarse GMRES 1 it {t_c1:.2f}s / 8 it {t_c8:.2f}s, A-DEF1 with "
-                   f"1 inner it {t_d1:.2f}s (sample {sum(res[nthr][1]):.1f}s); extrapolated to "
-                   f"{info['outer_iters']} outer + {info['inner_iters_total']} inner iterations "
-                   f"= {est:.0f}s per solve; the same sample with 1 thread "
-                   f"({sum(res[1][1]):.1f}s) gives {res[1][0]:.0f}s per solve; host {model}"),
+        "sample": (f"C oracle with {nthr} threads on the full {w.nx}x{w.ny} grid, coarse "
+                   f"restart {m}: A_h apply {t_a:.2f}s, coarse GMRES {m} it {t_m:.2f}s / "
+                   f"{2 * m} it {t_2m:.2f}s, A-DEF1 with {m} inner it {t_d:.2f}s (sample "
+                   f"{sum(res[nthr][1]):.1f}s); extrapolated to {info['outer_iters']} outer + "
+                   f"{info['inner_iters_total']} inner iterations = {est:.0f}s per solve; the "
+                   f"same sample with 1 thread ({sum(res[1][1]):.1f}s) gives {res[1][0]:.0f}s "
+                   f"per solve; host {model}"),
         "est_seconds_per_solve": est,
         "value_1thread": 1.0 / res[1][0],
         "host": model,
@@ -495,9 +495,11 @@ def main():
         }
     if not a.no_cpu_baseline:
         if w.nx * w.ny <= 300 * 300:
-            line["cpu_baseline"] = cpu_baseline_full(w, S.opts.coarsest_nodes)
+            line["cpu_baseline"] = cpu_baseline_full(w, S.opts.coarsest_nodes,
+                                                     opts["coarse_restart"])
         else:
-            line["cpu_baseline"] = cpu_baseline(w, last, S.opts.coarsest_nodes)
+            line["cpu_baseline"] = cpu_baseline(w, last, S.opts.coarsest_nodes,
+                                                opts["coarse_restart"])
     print(json.dumps(line), flush=True)
 
 

@@ -26,7 +26,7 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotu
 
 VC_TAIL = (0, 70000, 300000, 1100000)
 GRAPHS = (0, 1)
-COARSE_RESTART = (10, 15, 20, 30)
+COARSE_RESTART = (8, 10, 12, 15, 20, 30)
 
 
 def arch() -> str:
