@@ -169,16 +169,21 @@ def test_mixed_solve_equal_iterations(H, ora, prec):
 
 
 def test_mixed_wedge_full_size(H, ora):
-    """The 1153 x 1921 wedge at 40 Hz: the mixed-precision (both settings) and
-    FP64 solves all reach the FP64 tolerance (true residual recomputed by the
-    oracle operator) with the same outer count to within one, and their
-    solutions agree to the level two 1e-6-residual solutions can."""
+    """The 1153 x 1921 wedge at 40 Hz against a whole FP64 oracle solve: the
+    FP64 and the mixed-precision (both settings) solves all reach the FP64
+    tolerance (true residual recomputed by the oracle operator) within one
+    outer iteration of the oracle, and every solution matches the oracle's to
+    1e-5.  (Measured: all four take 14 outer / 784 inner iterations; the
+    differences are 2.7e-14 in FP64, 6.7e-11 with the complex64 V-cycle and
+    8.4e-11 with the complex64 basis as well: FGMRES absorbs the rounding of
+    the preconditioner.)"""
     w = inputs.wedge()
-    sols = {}
+    b = w.rhs()
+    sols, P = {}, None
     for prec in (0, MIXED, C64B):
         S, P = _wedge_pair(H, ora, w, precision=prec)
-        b = w.rhs()
         x, info = S.solve(dev(b))
+        S.close()
         xg = host(x)
         r = ora.helm_apply(P, xg) - b
         relres = np.linalg.norm(r) / np.linalg.norm(b)
@@ -186,8 +191,12 @@ def test_mixed_wedge_full_size(H, ora):
         sols[prec] = (xg, info[0]["outer_iters"])
         print(f"wedge 1153x1921 precision={prec}: outer {info[0]['outer_iters']}, "
               f"inner {info[0]['inner_iters_total']}, relres {relres:.3e}")
-    for prec in MIXED_MODES:
-        assert abs(sols[0][1] - sols[prec][1]) <= 1
-        d = rel(sols[prec][0], sols[0][0])
-        print(f"wedge 1153x1921 precision={prec}: ||x_mixed - x_fp64|| / ||x_fp64|| = {d:.3e}")
-        assert d <= 1e-4
+    xo, io = ora.fgmres(P, b, restart=w.restart, tol=w.tol, maxit=200)
+    assert io.converged
+    print(f"wedge 1153x1921 oracle: outer {io.iters}, inner {io.inner_total}, "
+          f"relres {io.relres:.3e}")
+    for prec in (0, MIXED, C64B):
+        assert abs(sols[prec][1] - io.iters) <= 1
+        d = rel(sols[prec][0], xo)
+        print(f"wedge 1153x1921 precision={prec}: ||x - x_oracle|| / ||x_oracle|| = {d:.3e}")
+        assert d <= 1e-5
