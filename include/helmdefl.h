@@ -166,6 +166,8 @@ typedef struct {
                               the handle's stream; of the whole batch in a
                               batched solve)                                    */
     double t_vcycle_ms;    /* GPU time of the fine-grid CSLP V-cycles (as above) */
+    int reorth_steps;      /* Arnoldi steps (outer and inner) that took a second
+                              Gram-Schmidt pass (the cancellation test fired)  */
 } helm_solve_info;
 
 typedef struct helm_ctx helm_ctx;

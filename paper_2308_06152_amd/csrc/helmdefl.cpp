@@ -165,6 +165,7 @@ struct BatchWS {
     int *gmask = nullptr;
     std::vector<std::pair<int, hipGraphExec_t>> gchunk;
     bool graph_off = false;
+    std::vector<int> reo;  // per right-hand side: Arnoldi steps with a second pass
 };
 
 }  // namespace
@@ -197,7 +198,7 @@ struct helm_ctx {
     // reductions
     cd *part = nullptr, *partn = nullptr;
     int part_blocks = 0;
-    long long n_arnoldi = 0, n_reorth = 0;
+    long long n_arnoldi = 0, n_reorth = 0;  // Arnoldi steps, and those with a second pass
     cd *hbuf = nullptr, *ydev = nullptr;
     cd *sig = nullptr;   // 1/||u_i|| of the lazily normalised inner basis
     cd *hpin = nullptr;  // pinned: two Arnoldi read-back slots, y staging, norm
@@ -445,17 +446,18 @@ int step_readback(helm_ctx *h, int slot)
 
 // Arnoldi step of the inner solve on a lazily normalised basis: V[i] holds
 // u_i with v_i = sig[i] u_i.  The new vector w = A z already sits in V[j1];
-// it is orthogonalised in place (same conditional second pass as above) and
+// it is orthogonalised in place by one classical Gram-Schmidt pass and
 // sig[j1] = 1/||w'|| is stored, so no scaling pass is needed.  Everything is
 // enqueued; the norm reduction also writes the step's scalars to the host
 // slot hpub + slot * HBUF, and (with readback) ev_slot[slot] is recorded.
-// arnoldi_finish() waits for that event.
+// arnoldi_finish() waits for that event and evaluates the cancellation test;
+// the rare second pass is then arnoldi_repair(), queued by the host.
 int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int lev, int slot,
                          bool readback = true)
 {
     const int nb = krylov_blocks(n), nbu = krylov_blocks(n, 1, KB_UPDATE);
     cd *w = V + (size_t)j1 * ld;
-    cd *h1 = h->hbuf, *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
+    cd *h1 = h->hbuf, *nr = h->hbuf + 2 * PSTRIDE;
     {
         Timed tm(h, HELM_K_DOT, lev, 16.0 * (j1 + 1) * n);
         HCHK(launch_mdot(V, ld, j1, w, n, h->part, 1, nullptr, 0, h->st));
@@ -465,26 +467,71 @@ int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int le
         Timed tm(h, HELM_K_UPDATE, lev, 16.0 * (j1 + 2) * n);
         HCHK(launch_mupdate(w, V, ld, j1, h1, n, h->partn, nullptr, 0, h->sig, h->st));
     }
-    HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
-    HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
-    HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
     HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, 2 * PSTRIDE + 1,
                              h->hpub_dev + slot * HBUF, h->st));
     if (readback) RCHK(step_readback(h, slot));
     return HELM_OK;
 }
 
-int arnoldi_finish(helm_ctx *h, int j1, int slot, zc *col, double *hn)
+// The cancellation test of the first pass, from the published projections
+// hb[0..j1) and hb[j1].x = ||w||^2: a second pass is needed when
+// ||w'||^2 = ||w||^2 - sum |h_i|^2 falls to half of ||w||^2 or below (the
+// expression and order of need_reorth on the device, with explicit FMAs).
+bool need_reorth_host(const cd *hb, int j1)
+{
+    double s = 0.0;
+    for (int i = 0; i < j1; i++) s = std::fma(hb[i].x, hb[i].x, std::fma(hb[i].y, hb[i].y, s));
+    const double w2 = hb[j1].x;
+    return !(w2 - s > 0.5 * w2);
+}
+
+// Wait for an inner step's scalars (slot `slot`).  col[0..j1) = the
+// projections, *hn = ||w'||.  With `lazy` (a step of arnoldi_lazy_enqueue:
+// first pass only) *repair tells whether the cancellation test asks for a
+// second pass; otherwise the step's own second pass (h2) is added in.
+int arnoldi_finish(helm_ctx *h, int j1, int slot, zc *col, double *hn, bool lazy = false,
+                   bool *repair = nullptr)
 {
     HCHK(hipEventSynchronize(h->ev_slot[slot]));
     const cd *hp = h->hpub + slot * HBUF;
     bool reorth = false;
     for (int i = 0; i < j1; i++) {
-        col[i] = zc(hp[i].x + hp[PSTRIDE + i].x, hp[i].y + hp[PSTRIDE + i].y);
-        reorth |= hp[PSTRIDE + i].x != 0.0 || hp[PSTRIDE + i].y != 0.0;
+        if (lazy) {
+            col[i] = zc(hp[i].x, hp[i].y);
+        } else {
+            col[i] = zc(hp[i].x + hp[PSTRIDE + i].x, hp[i].y + hp[PSTRIDE + i].y);
+            reorth |= hp[PSTRIDE + i].x != 0.0 || hp[PSTRIDE + i].y != 0.0;
+        }
     }
     h->n_arnoldi++;
     h->n_reorth += reorth;
+    *hn = hp[2 * PSTRIDE].x;
+    if (repair) *repair = lazy && need_reorth_host(hp, j1);
+    return HELM_OK;
+}
+
+// The second Gram-Schmidt pass of the inner step that produced V[j1], queued
+// by the host after arnoldi_finish() asked for it (behind whatever step was
+// already queued): h2 = V^H w', w'' = w' - V h2 in place, sig[j1] =
+// 1/||w''||, and the slot republished (its h2 and norm; its h1 part then
+// holds the later step's projections and is not read).  Waits for the slot;
+// col[0..j1) += h2, *hn = ||w''||.
+int arnoldi_repair(helm_ctx *h, int j1, int slot, zc *col, double *hn)
+{
+    const size_t n = h->L[1].n(), ld = n;
+    const int nb = krylov_blocks(n), nbu = krylov_blocks(n, 1, KB_UPDATE);
+    cd *V = h->Vc, *w = h->Vc + (size_t)j1 * ld;
+    cd *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
+    HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, nullptr, 0, h->st));
+    HCHK(launch_reduce(h->part, nb, j1, h2, 0, nullptr, 0, h->sig, j1, nullptr, h->st));
+    HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, nullptr, 0, h->sig, h->st));
+    HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, 2 * PSTRIDE + 1,
+                             h->hpub_dev + slot * HBUF, h->st));
+    RCHK(step_readback(h, slot));
+    HCHK(hipEventSynchronize(h->ev_slot[slot]));
+    const cd *hp = h->hpub + slot * HBUF;
+    for (int i = 0; i < j1; i++) col[i] += zc(hp[PSTRIDE + i].x, hp[PSTRIDE + i].y);
+    h->n_reorth++;
     *hn = hp[2 * PSTRIDE].x;
     return HELM_OK;
 }
@@ -857,7 +904,15 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
         for (int j = 0; j < steps; j++) {
             if (j + 1 < steps) RCHK(step(j + 1, (j + 1) & 1));
             double hn;
-            RCHK(arnoldi_finish(h, j + 1, j & 1, col.data(), &hn));
+            bool repair = false;
+            RCHK(arnoldi_finish(h, j + 1, j & 1, col.data(), &hn, !b32, &repair));
+            if (repair) {
+                // second pass on v_{j+1}, queued behind the speculative step
+                // j + 1, which read the vector before it; that step is then
+                // queued again on the repaired vector
+                RCHK(arnoldi_repair(h, j + 1, j & 1, col.data(), &hn));
+                if (j + 1 < steps) RCHK(step(j + 1, (j + 1) & 1));
+            }
             const double res = gv.add_column(j, col.data(), hn);
             it++;
             jend = j + 1;
@@ -1475,11 +1530,15 @@ int arnoldi_lazy_b(helm_ctx *h, int j1, int slot, const int *dm, int nact)
 
 // Projections (both passes summed) and norm of right-hand side b from a
 // read-back slot.
-double read_col(const BatchWS *W, int slot, int b, int j1, zc *col)
+double read_col(BatchWS *W, int slot, int b, int j1, zc *col)
 {
     const cd *hp = W->hpin + ((size_t)slot * W->B + b) * HB;
-    for (int i = 0; i < j1; i++)
+    bool reorth = false;
+    for (int i = 0; i < j1; i++) {
         col[i] = zc(hp[i].x + hp[PSTRIDE + i].x, hp[i].y + hp[PSTRIDE + i].y);
+        reorth |= hp[PSTRIDE + i].x != 0.0 || hp[PSTRIDE + i].y != 0.0;
+    }
+    if (reorth && (int)W->reo.size() > b) W->reo[b]++;
     return hp[2 * PSTRIDE].x;
 }
 
@@ -1781,6 +1840,7 @@ int solve_b(helm_ctx *h, const cd *b, cd *x, int B, helm_solve_info *info)
     const auto t0 = std::chrono::steady_clock::now();
     RCHK(ensure_batch(h, B, true));
     BatchWS *W = h->bw;
+    W->reo.assign(B, 0);
     const size_t n = h->L[0].n(), ld = (size_t)B * n;
     const int m = h->o.restart;
     const Lev L0 = h->lev(0);
@@ -1888,6 +1948,7 @@ int solve_b(helm_ctx *h, const cd *b, cd *x, int B, helm_solve_info *info)
     for (int q = 0; q < B; q++) {
         inf[q].t_solve_ms = ms;
         if (!inf[q].converged && force <= 0) rc = HELM_ENOCONV;
+        inf[q].reorth_steps = W->reo[q];
         if (info) info[q] = inf[q];
     }
     return rc;
@@ -2391,10 +2452,12 @@ static int solve_dispatch(helm_ctx *h, const void *b, void *x, int nrhs, helm_so
             cd *xq = (cd *)x + q * n;
             helm_solve_info *iq = info ? info + q : nullptr;
             phase_begin(h);
+            const long long r0 = h->n_reorth;
             const int rc = h->o.outer == HELM_OUTER_GCR         ? solve_gcr(h, bq, xq, iq)
                            : h->o.outer == HELM_OUTER_GMRES_LEFT ? solve_left(h, bq, xq, iq)
                                                                  : solve_one(h, bq, xq, iq);
             set_phases(h, iq, 1);
+            if (iq) iq->reorth_steps = (int)(h->n_reorth - r0);
             if (rc != HELM_OK && rc != HELM_ENOCONV) return rc;
             if (rc == HELM_ENOCONV) worst = rc;
         }

@@ -60,7 +60,7 @@ class SolveInfo(ctypes.Structure):
                 ("inner_iters_max", ctypes.c_int), ("converged", ctypes.c_int),
                 ("relres", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_setup_ms", ctypes.c_double), ("t_coarse_ms", ctypes.c_double),
-                ("t_vcycle_ms", ctypes.c_double)]
+                ("t_vcycle_ms", ctypes.c_double), ("reorth_steps", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
