@@ -214,10 +214,16 @@ struct helm_ctx {
     cd *adjb = nullptr;              // adjoint solve right-hand sides
     size_t adjb_n = 0;
 
-    // captured coarse-GMRES steps, one per basis index (null until first use);
-    // graph_off after a capture failed
-    std::vector<hipGraphExec_t> gstep;
+    // captured coarse-GMRES steps, one per basis index (null until first use),
+    // without and with the device-side second Gram-Schmidt pass; graph_off
+    // after a capture failed
+    std::vector<hipGraphExec_t> gstep, gstep2;
     bool graph_off = false;
+    // moving average of how often an inner step's cancellation test fires
+    // (0.9 old + 0.1 new): from 1/8 on, the steps launch the second pass
+    // themselves (decided on the device) rather than leave it to the host;
+    // both give the same iterates
+    double reo_rate = 0.0;
 
     // kernel timing
     int t_cls = -1, t_lev = -1;
@@ -451,13 +457,15 @@ int step_readback(helm_ctx *h, int slot)
 // enqueued; the norm reduction also writes the step's scalars to the host
 // slot hpub + slot * HBUF, and (with readback) ev_slot[slot] is recorded.
 // arnoldi_finish() waits for that event and evaluates the cancellation test;
-// the rare second pass is then arnoldi_repair(), queued by the host.
+// the second pass is then arnoldi_repair(), queued by the host.  With dev2
+// the step launches the second pass itself, each kernel of it returning at
+// once unless the same test, evaluated on the device, fires (h2 = 0 then).
 int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int lev, int slot,
-                         bool readback = true)
+                         bool readback = true, bool dev2 = false)
 {
     const int nb = krylov_blocks(n), nbu = krylov_blocks(n, 1, KB_UPDATE);
     cd *w = V + (size_t)j1 * ld;
-    cd *h1 = h->hbuf, *nr = h->hbuf + 2 * PSTRIDE;
+    cd *h1 = h->hbuf, *h2 = h->hbuf + PSTRIDE, *nr = h->hbuf + 2 * PSTRIDE;
     {
         Timed tm(h, HELM_K_DOT, lev, 16.0 * (j1 + 1) * n);
         HCHK(launch_mdot(V, ld, j1, w, n, h->part, 1, nullptr, 0, h->st));
@@ -466,6 +474,11 @@ int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int le
     {
         Timed tm(h, HELM_K_UPDATE, lev, 16.0 * (j1 + 2) * n);
         HCHK(launch_mupdate(w, V, ld, j1, h1, n, h->partn, nullptr, 0, h->sig, h->st));
+    }
+    if (dev2) {
+        HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
+        HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
+        HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
     }
     HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, 2 * PSTRIDE + 1,
                              h->hpub_dev + slot * HBUF, h->st));
@@ -486,11 +499,12 @@ bool need_reorth_host(const cd *hb, int j1)
 }
 
 // Wait for an inner step's scalars (slot `slot`).  col[0..j1) = the
-// projections, *hn = ||w'||.  With `lazy` (a step of arnoldi_lazy_enqueue:
-// first pass only) *repair tells whether the cancellation test asks for a
-// second pass; otherwise the step's own second pass (h2) is added in.
+// projections, *hn = ||w'||.  With `lazy` (a step of arnoldi_lazy_enqueue
+// without its second pass) *repair tells whether the cancellation test asks
+// for one; otherwise the step's own second pass (h2) is added in, and *fired
+// tells whether it ran.
 int arnoldi_finish(helm_ctx *h, int j1, int slot, zc *col, double *hn, bool lazy = false,
-                   bool *repair = nullptr)
+                   bool *repair = nullptr, bool *fired = nullptr)
 {
     HCHK(hipEventSynchronize(h->ev_slot[slot]));
     const cd *hp = h->hpub + slot * HBUF;
@@ -507,6 +521,7 @@ int arnoldi_finish(helm_ctx *h, int j1, int slot, zc *col, double *hn, bool lazy
     h->n_reorth += reorth;
     *hn = hp[2 * PSTRIDE].x;
     if (repair) *repair = lazy && need_reorth_host(hp, j1);
+    if (fired) *fired = reorth;
     return HELM_OK;
 }
 
@@ -753,13 +768,13 @@ int coarse_apply(helm_ctx *h, const cd *x, const cd *b, cd *y)
 // basis slot j+1, then the lazily normalised orthogonalisation, whose last
 // kernel writes the step's scalars to host slot `slot` (and, with readback,
 // the slot's event).
-int inner_step_enqueue(helm_ctx *h, int j, int slot, bool readback = true)
+int inner_step_enqueue(helm_ctx *h, int j, int slot, bool readback = true, bool dev2 = false)
 {
     const size_t nc = h->L[1].n();
     cd *z = h->Zc + (size_t)j * nc;
     RCHK(vcycle(h, 1, h->Vc + (size_t)j * nc, z, 0, nullptr, h->sig + j));
     RCHK(coarse_apply(h, z, nullptr, h->Vc + (size_t)(j + 1) * nc));
-    return arnoldi_lazy_enqueue(h, h->Vc, nc, j + 1, nc, 1, slot, readback);
+    return arnoldi_lazy_enqueue(h, h->Vc, nc, j + 1, nc, 1, slot, readback, dev2);
 }
 
 // The same step on the complex64 basis (mixed precision): A_2h z is formed
@@ -807,15 +822,17 @@ int inner_step_enqueue32(helm_ctx *h, int j, int slot, bool readback = true)
 // step's last kernel), so the graph holds kernel nodes only.  Off while
 // kernel timing is on; a failed capture turns graphs off for this context and
 // the step is launched directly.
-int inner_step_run(helm_ctx *h, int j, int slot)
+int inner_step_run(helm_ctx *h, int j, int slot, bool dev2)
 {
     const bool b32 = h->basis32;
     auto direct = [&](bool rb) {
-        return b32 ? inner_step_enqueue32(h, j, slot, rb) : inner_step_enqueue(h, j, slot, rb);
+        return b32 ? inner_step_enqueue32(h, j, slot, rb)
+                   : inner_step_enqueue(h, j, slot, rb, dev2);
     };
     if (!h->o.graphs || h->graph_off || h->t_cls >= 0) return direct(true);
-    if ((int)h->gstep.size() <= j) h->gstep.resize(j + 1, nullptr);
-    if (!h->gstep[j]) {
+    std::vector<hipGraphExec_t> &gs = dev2 && !b32 ? h->gstep2 : h->gstep;
+    if ((int)gs.size() <= j) gs.resize(j + 1, nullptr);
+    if (!gs[j]) {
         if (hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             (void)hipGetLastError();
             h->graph_off = true;
@@ -827,7 +844,7 @@ int inner_step_run(helm_ctx *h, int j, int slot)
         hipGraphExec_t ex = nullptr;
         if (rc == HELM_OK && ec == hipSuccess && g &&
             hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
-            h->gstep[j] = ex;
+            gs[j] = ex;
         } else {
             (void)hipGetLastError();
             h->graph_off = true;
@@ -835,7 +852,7 @@ int inner_step_run(helm_ctx *h, int j, int slot)
         if (g) (void)hipGraphDestroy(g);
         if (h->graph_off) return direct(true);
     }
-    HCHK(hipGraphLaunch(h->gstep[j], h->st));
+    HCHK(hipGraphLaunch(gs[j], h->st));
     return step_readback(h, slot);
 }
 
@@ -899,13 +916,20 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
         const int steps = std::min(m, cap - it);
         int jend = 0;
         bool stop = false;
-        auto step = [&](int j, int slot) { return inner_step_run(h, j, slot); };
+        // per slot: whether its step launched the second pass itself
+        bool dev2[2] = {true, true};
+        auto step = [&](int j, int slot) {
+            dev2[slot] = b32 || h->reo_rate >= 0.125;
+            return inner_step_run(h, j, slot, dev2[slot]);
+        };
         RCHK(step(0, 0));
         for (int j = 0; j < steps; j++) {
             if (j + 1 < steps) RCHK(step(j + 1, (j + 1) & 1));
             double hn;
-            bool repair = false;
-            RCHK(arnoldi_finish(h, j + 1, j & 1, col.data(), &hn, !b32, &repair));
+            bool repair = false, fired = false;
+            RCHK(arnoldi_finish(h, j + 1, j & 1, col.data(), &hn, !dev2[j & 1], &repair,
+                                &fired));
+            h->reo_rate = 0.9 * h->reo_rate + ((repair || fired) ? 0.1 : 0.0);
             if (repair) {
                 // second pass on v_{j+1}, queued behind the speculative step
                 // j + 1, which read the vector before it; that step is then
@@ -2035,10 +2059,12 @@ int setup_coarsest(helm_ctx *h, const std::vector<std::vector<double>> &khost)
 
 void release(helm_ctx *h)
 {
-    for (hipGraphExec_t &e : h->gstep)
-        if (e) (void)hipGraphExecDestroy(e);
-    h->gstep.clear();
     if (!h) return;
+    for (auto *gs : {&h->gstep, &h->gstep2}) {
+        for (hipGraphExec_t &e : *gs)
+            if (e) (void)hipGraphExecDestroy(e);
+        gs->clear();
+    }
     if (h->st) (void)hipStreamSynchronize(h->st);
     for (int l = 0; l < h->nlev; l++) {
         dfree(h->L[l].kdev);
