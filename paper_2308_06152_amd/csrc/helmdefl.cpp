@@ -4,7 +4,9 @@
 //
 // Every arithmetic step of the solve runs in the kernels of kernels.hip; the
 // host only launches them, reads the Krylov scalars back (one small copy per
-// Arnoldi step) and does the O(m^2) Givens / least-squares work of GMRES.
+// Arnoldi step), does the O(m^2) Givens / least-squares work of GMRES and,
+// on the single-source inner path, evaluates the Gram-Schmidt cancellation
+// test on the scalars it has read, to queue the rare second pass.
 #include "helmdefl.h"
 
 #include <hip/hip_runtime.h>
