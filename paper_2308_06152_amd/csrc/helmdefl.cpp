@@ -62,7 +62,10 @@ namespace {
 
 constexpr int MAXLEV = 40;
 constexpr int MAX_COARSEST = 2048;  // nodes of the coarsest multigrid level
-constexpr int HBUF = 2 * PSTRIDE + 2;  // h1[64], h2[64], norm, spare
+// device scalars of the inner solve: h1[64], h2[64], norm, the constant 1, and
+// the norm of a restart's residual (published with the cycle's first step)
+constexpr int HBUF = 2 * PSTRIDE + 3;
+constexpr int HB_BETA = 2 * PSTRIDE + 2;
 
 #define HCHK(call)                                   \
     do {                                             \
@@ -208,6 +211,7 @@ struct helm_ctx {
     // (written by the device; hpub_dev is the device's address of hpub)
     cd *hpub = nullptr, *hpub_dev = nullptr;
     hipEvent_t ev_slot[2] = {nullptr, nullptr};
+    hipEvent_t ev_y = nullptr;  // the last upload of y from its pinned staging
     // outer FGMRES (allocated on first solve)
     int m = 0;
     cd *V = nullptr, *Z = nullptr, *w = nullptr, *bm = nullptr;
@@ -387,14 +391,21 @@ bool coarsenable(int nx, int ny) { return nx >= 5 && ny >= 5 && (nx & 1) && (ny 
 // least-squares solution staging at 2*HBUF, the norm read-back at 3*HBUF.
 constexpr int PIN_Y = 2 * HBUF, PIN_NORM = 3 * HBUF, PIN_TOTAL = 4 * HBUF;
 
+// ||v|| of a device vector into out_dev[0] (device), and 1/||v|| into
+// sig_out[0] when given; nothing is read back.
+int vnorm_enqueue(helm_ctx *h, const cd *v, size_t n, cd *out_dev, cd *sig_out)
+{
+    const int nb = krylov_blocks(n);
+    HCHK(launch_mdot(nullptr, 0, 0, v, n, h->part, 1, nullptr, 0, h->st));
+    HCHK(launch_reduce(h->part, nb, 1, out_dev, 2, nullptr, 0, nullptr, 0, sig_out, h->st));
+    return HELM_OK;
+}
+
 // ||v|| of a device vector (synchronises); also stores 1/||v|| in sig_out[0]
 // when given.
 int vnorm(helm_ctx *h, const cd *v, size_t n, double *out, cd *sig_out = nullptr)
 {
-    const int nb = krylov_blocks(n);
-    HCHK(launch_mdot(nullptr, 0, 0, v, n, h->part, 1, nullptr, 0, h->st));
-    HCHK(launch_reduce(h->part, nb, 1, h->hbuf + 2 * PSTRIDE, 2, nullptr, 0, nullptr, 0, sig_out,
-                       h->st));
+    RCHK(vnorm_enqueue(h, v, n, h->hbuf + 2 * PSTRIDE, sig_out));
     HCHK(hipMemcpyAsync(h->hpin + PIN_NORM, h->hbuf + 2 * PSTRIDE, sizeof(cd),
                         hipMemcpyDeviceToHost, h->st));
     HCHK(hipStreamSynchronize(h->st));
@@ -482,7 +493,7 @@ int arnoldi_lazy_enqueue(helm_ctx *h, cd *V, size_t ld, int j1, size_t n, int le
         HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
         HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
     }
-    HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, 2 * PSTRIDE + 1,
+    HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, HBUF,
                              h->hpub_dev + slot * HBUF, h->st));
     if (readback) RCHK(step_readback(h, slot));
     return HELM_OK;
@@ -542,7 +553,7 @@ int arnoldi_repair(helm_ctx *h, int j1, int slot, zc *col, double *hn)
     HCHK(launch_mdot(V, ld, j1, w, n, h->part, 0, nullptr, 0, h->st));
     HCHK(launch_reduce(h->part, nb, j1, h2, 0, nullptr, 0, h->sig, j1, nullptr, h->st));
     HCHK(launch_mupdate(w, V, ld, j1, h2, n, h->partn, nullptr, 0, h->sig, h->st));
-    HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, 2 * PSTRIDE + 1,
+    HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, HBUF,
                              h->hpub_dev + slot * HBUF, h->st));
     RCHK(step_readback(h, slot));
     HCHK(hipEventSynchronize(h->ev_slot[slot]));
@@ -555,12 +566,14 @@ int arnoldi_repair(helm_ctx *h, int j1, int slot, zc *col, double *hn)
 
 int upload_y(helm_ctx *h, const std::vector<zc> &y)
 {
+    // the staging buffer may still be read by the previous upload's copy
+    // (in practice long done: the host has waited on later work since)
+    HCHK(hipEventSynchronize(h->ev_y));
     for (size_t i = 0; i < y.size(); i++)
         h->hpin[PIN_Y + i] = make_double2(y[i].real(), y[i].imag());
     HCHK(hipMemcpyAsync(h->ydev, h->hpin + PIN_Y, y.size() * sizeof(cd), hipMemcpyHostToDevice,
                         h->st));
-    // the pinned staging buffer is reused by the next readback: wait for the copy
-    HCHK(hipStreamSynchronize(h->st));
+    HCHK(hipEventRecord(h->ev_y, h->st));
     return HELM_OK;
 }
 
@@ -802,7 +815,7 @@ int arnoldi_lazy_enqueue32(helm_ctx *h, size_t n, int j1, int slot, bool readbac
     HCHK(launch_mdot32(V, ld, j1, w, n, h->part, 0, h1, j1, h->st));
     HCHK(launch_reduce(h->part, nb, j1, h2, 0, h1, j1, h->sig, j1, nullptr, h->st));
     HCHK(launch_mupdate32(w, V, ld, j1, h2, n, h->partn, h1, j1, h->sig, h->st));
-    HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, 2 * PSTRIDE + 1,
+    HCHK(launch_norm_publish(h->partn, nbu, nr, h->sig + j1, h->hbuf, HBUF,
                              h->hpub_dev + slot * HBUF, h->st));
     if (readback) RCHK(step_readback(h, slot));
     return HELM_OK;
@@ -897,27 +910,41 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
     if (bnorm == 0.0) return HELM_OK;
     Givens gv(m);
     std::vector<zc> col(m + 1), y;
-    bool first = true;
+    bool first = true, stop = false;
     for (;;) {
-        double beta;
+        // A cycle that ended at its restart length (its estimate still above
+        // the tolerance) restarts without reading the residual norm back: the
+        // norm stays on the device (hbuf[HB_BETA], 1/beta in sig[0]) and
+        // reaches the host with the next cycle's first step, which is queued
+        // at once; the tests on it are made then, and a cycle found not to be
+        // needed is dropped (its queued steps write nothing read afterwards).
+        // After a cycle whose estimate met the tolerance, the true residual is
+        // read back first, as that restart usually ends the solve.
+        const bool late_beta = !first && !stop;
+        double beta = bnorm;  // first cycle: sig[0] = 1/||b|| was stored by vnorm
         if (first) {
             if (b32)
                 RCHK(basis32_set0(h, b));
             else
                 HCHK(hipMemcpyAsync(h->Vc, b, nc * sizeof(cd), hipMemcpyDeviceToDevice, h->st));
-            beta = bnorm;  // sig[0] = 1/||b|| was stored by vnorm
         } else {
             cd *r0 = b32 ? h->wtmp : h->Vc;
             RCHK(coarse_apply(h, x, b, r0));
-            RCHK(vnorm(h, r0, nc, &beta, h->sig));
+            if (late_beta)
+                RCHK(vnorm_enqueue(h, r0, nc, h->hbuf + HB_BETA, h->sig));
+            else
+                RCHK(vnorm(h, r0, nc, &beta, h->sig));
             if (b32) RCHK(basis32_set0(h, r0));
         }
-        if (!fixed && beta <= tol * bnorm) break;
-        if (it >= cap || beta == 0.0) break;
-        gv.start(beta);
+        if (!late_beta) {
+            if (!fixed && beta <= tol * bnorm) break;
+            if (it >= cap || beta == 0.0) break;
+            gv.start(beta);
+        }
         const int steps = std::min(m, cap - it);
         int jend = 0;
-        bool stop = false;
+        stop = false;
+        bool dropped = false;
         // per slot: whether its step launched the second pass itself
         bool dev2[2] = {true, true};
         auto step = [&](int j, int slot) {
@@ -927,6 +954,15 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
         RCHK(step(0, 0));
         for (int j = 0; j < steps; j++) {
             if (j + 1 < steps) RCHK(step(j + 1, (j + 1) & 1));
+            if (j == 0 && late_beta) {
+                HCHK(hipEventSynchronize(h->ev_slot[0]));
+                beta = h->hpub[HB_BETA].x;
+                if ((!fixed && beta <= tol * bnorm) || beta == 0.0) {
+                    dropped = true;
+                    break;
+                }
+                gv.start(beta);
+            }
             double hn;
             bool repair = false, fired = false;
             RCHK(arnoldi_finish(h, j + 1, j & 1, col.data(), &hn, !dev2[j & 1], &repair,
@@ -947,6 +983,7 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
                 break;
             }
         }
+        if (dropped) break;
         // x += sum_i y_i M^-1 v_i, from the z_i the steps kept
         gv.solve(jend, y);
         RCHK(upload_y(h, y));
@@ -2100,6 +2137,7 @@ void release(helm_ctx *h)
     dfree(h->sig);
     for (auto e : h->ev_slot)
         if (e) (void)hipEventDestroy(e);
+    if (h->ev_y) (void)hipEventDestroy(h->ev_y);
     for (auto &p : h->pend) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -2257,6 +2295,12 @@ int create_impl(const helm_grid *g, const double *k_dev, double k_const, const h
             h->ev_slot[q] = nullptr;
             rc = HELM_EHIP;
         }
+    if (!rc && hipEventCreateWithFlags(&h->ev_y, hipEventDisableTiming) != hipSuccess) {
+        h->ev_y = nullptr;
+        rc = HELM_EHIP;
+    }
+    // record it once, so that the first upload's wait has an event to wait on
+    if (!rc && hipEventRecord(h->ev_y, h->st) != hipSuccess) rc = HELM_EHIP;
     if (!rc) {
         // slot 2*PSTRIDE+1 holds the constant 1 used to accumulate on the
         // coarsest level
