@@ -984,10 +984,13 @@ int coarse_solve(helm_ctx *h, const cd *b, cd *x, int *iters)
             }
         }
         if (dropped) break;
-        // x += sum_i y_i M^-1 v_i, from the z_i the steps kept
+        // x += sum_i y_i M^-1 v_i, from the z_i the steps kept, by the
+        // Gram-Schmidt update kernel (x -= sum_i c_i z_i with c = -y), which
+        // streams the z_i faster than the plain combination kernel
         gv.solve(jend, y);
+        for (zc &v : y) v = -v;
         RCHK(upload_y(h, y));
-        HCHK(launch_lincomb(h->Zc, nc, jend, h->ydev, x, nc, 1, h->st));
+        HCHK(launch_mupdate(x, h->Zc, nc, jend, h->ydev, nc, nullptr, nullptr, 0, nullptr, h->st));
         if (it >= cap) break;
         if (stop && fixed) break;
         first = false;
